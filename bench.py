@@ -1,0 +1,232 @@
+"""Benchmark: multirate SDC steps of the reacting Navier-Stokes right-hand side
+on one MI355X (FP64), with the oracle timed on the host cores as a baseline.
+
+Default workload: 128^3 periodic box, 9 species / 21 reactions, turbulent
+velocity (k^-5/3, u_rms 5 m/s) and a planar two-front flame slab, MRSDC mode
+1 with advection-diffusion on 4 Gauss-Lobatto nodes and chemistry on 5
+Gauss-Lobatto nodes per coarse interval, 6 sweeps.  One "step" is one MRSDC
+time step of the whole box.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                  [--no-cpu-baseline]
+
+Prints one JSON line.  value = SDC steps/s (inputs resident in HBM); the
+line also carries Mcell advection-diffusion and reaction evaluations per
+second, the roofline of the dominant kernel (average duration from HIP
+events recorded on the launch stream over the timed region) and the oracle
+baseline.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+# Algorithmic work per cell of each kernel kind (flops, HBM bytes), from the
+# operation counts of the method (not of the implementation): see the
+# measurement section of the design notes.
+def work_model(ns, n_coarse, n_fine_per_interval):
+    nu = 5 + ns
+    np_ = 8 + 3 * ns
+    # one direction of the stencil pass: convective divergence, narrow row sums
+    # shared per field and face pairs, first derivatives of the mixed and
+    # correction-velocity terms
+    narrow = (7 + ns) * 96 + (7 + 3 * ns) * 16
+    first = 11 * (36 + 12 * ns) / 3.0
+    dir_flops = narrow + first
+    dir_bytes = 8 * (nu + np_ + 4 + 2 * nu)            # read U, P, 4 gradients; read+write dU/dt
+    chem_flops = 32 * ns + 75 * (21 if ns == 9 else 84)
+    newton = 5 * ns * 20
+    r = n_fine_per_interval
+    fine_flops = r * (chem_flops + newton + nu * (2 * n_coarse + 6) + ns * (2 * r + 4))
+    fine_bytes = 8 * (2 * nu + (n_coarse + 2) * nu + (r + 1) * ns + r * ns)
+    return {
+        "dir_x": (dir_flops, dir_bytes), "dir_y": (dir_flops, dir_bytes), "dir_z": (dir_flops, dir_bytes),
+        "mr_fine": (fine_flops, fine_bytes),
+        "prims": (newton + 40 * ns, 8 * (nu + np_)),
+    }
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "api.cpp", "nsdc_internal.h", "launch.h"):
+        with open(os.path.join(ROOT, "paper_1309_7327_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs,
+    if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(workload, mech, n_cells_full):
+    """The oracle (plain C++ right-hand side + NumPy SDC driver) on a bounded
+    sample: one step of the same scheme on a 64^3 box of the same recipe,
+    scaled by cell count to the full box."""
+    import oracle
+    from oracle import sdc as osdc
+    from synth.workloads import WORKLOADS, make_primitives, time_step
+    wl = WORKLOADS[workload]
+    om = oracle.Mechanism(mech)
+    edge = 64
+    prim = make_primitives(workload, mech, shape_override=(edge,) * 3)
+    U0 = oracle.prim_to_cons(om, prim)
+    dt = time_step(workload)
+    sch = wl["scheme"]
+    dx = wl["dx"]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    if sch["kind"] == "sdc":
+        f = lambda U, t: oracle.rhs(om, U, dx, nthreads=threads)
+        osdc.sdc_run(f, U0, 0.0, dt, osdc.gauss_lobatto(sch["n_coarse"]), sch["sweeps"], 1)
+    else:
+        f1 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.AD, nthreads=threads)
+        f2 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.REACT, nthreads=threads)
+        t1, t2, pieces = osdc.mr_nodes(sch["n_coarse"], sch["n_fine"], sch["fine_repeat"])
+        osdc.mrsdc_run(f1, f2, U0, 0.0, dt, t1, t2, pieces, sch["sweeps"], 1)
+    el = time.perf_counter() - t0
+    return {"value": (edge ** 3 / n_cells_full) / el, "unit": "SDC steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one step of the same scheme on a {edge}^3 box of the same recipe "
+                      f"({el:.1f} s), scaled by cell count to {round(n_cells_full ** (1 / 3))}^3"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="box128_mrsdc")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (see the sharding notes in the design document)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1309_7327_amd import narrowsdc as N
+    from synth import mechanism
+    from synth.workloads import WORKLOADS, make_primitives, time_step
+
+    wl = WORKLOADS[args.workload]
+    assert "shape" in wl, "bench runs the single-box workloads"
+    mech = mechanism.load(wl["mech"])
+    ns = mech["ns"]
+    nz, ny, nx = wl["shape"]
+    ncell = nx * ny * nz
+    dx = wl["dx"]
+    dt = time_step(args.workload)
+    sch_d = wl["scheme"]
+    if sch_d["kind"] == "sdc":
+        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], 0, 1)
+        r = 0
+    else:
+        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], sch_d["n_fine"], sch_d["fine_repeat"])
+        r = (sch_d["n_fine"] - 1) * sch_d["fine_repeat"]
+
+    torch.cuda.set_device(0)
+    ctx = N.Context(0)
+    ctx.set_mechanism(mech)
+    prim = make_primitives(args.workload, mech)
+    bx = N.box(nx, ny, nz, dx)
+    U = torch.zeros(N.ghosted_shape(5 + ns, nz, ny, nx), dtype=torch.float64, device="cuda")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    ctx.prim_to_cons(bx, dev(prim["p"]), dev(prim["T"]), dev(prim["Y"]), dev(prim["u"]), U)
+    del prim
+    ws, nb = N.workspace(ctx, [bx], sch)
+    stream = torch.cuda.current_stream()
+
+    if args.warmup > 0:
+        ctx.sdc_step(bx, U, dt, args.warmup, sch, ws, nb)
+    ctx.check_status()
+    torch.cuda.synchronize()
+
+    lib = N._lib
+    lib.sdc_profile_enable(ctx.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sdc_step(bx, U, dt, args.steps, sch, ws, nb)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check_status()
+    import ctypes
+    tot = (ctypes.c_double * 16)()
+    cnt = (ctypes.c_int * 16)()
+    nk = lib.sdc_profile_read(ctx.h, ctypes.c_void_p(stream.cuda_stream), tot, cnt)
+    lib.sdc_kernel_name.restype = ctypes.c_char_p
+    lib.sdc_kernel_name.argtypes = [ctypes.c_int]
+    kern = {lib.sdc_kernel_name(i).decode(): (tot[i], cnt[i]) for i in range(nk) if cnt[i] > 0}
+    lib.sdc_profile_enable(ctx.h, 0)
+
+    el = t1 - t0
+    steps_per_s = args.steps / el
+    M1 = sch_d["n_coarse"] - 1
+    n_ad = args.steps * sch_d["sweeps"] * M1
+    n_r = args.steps * sch_d["sweeps"] * M1 * r if r else n_ad
+    model = work_model(ns, sch_d["n_coarse"], r)
+    dominant = max(kern, key=lambda k: kern[k][0])
+    dur_ms = kern[dominant][0] / kern[dominant][1]
+    if dominant in model:
+        fl, by = model[dominant]
+        units = ncell
+        flops = fl * units
+        bytes_ = by * units
+        ai = flops / bytes_
+        if ai * HBM_PEAK_GBS * 1e9 < FP64_PEAK_TFLOPS * 1e12:
+            roof = {"bound": "hbm", "achieved": bytes_ / (dur_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s"}
+        else:
+            roof = {"bound": "alu", "achieved": flops / (dur_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None}
+    roof["kernel"] = dominant
+    roof["avg_launch_ms"] = dur_ms
+    roof["traffic"] = stored_traffic(dominant, args.workload)
+
+    out = {
+        "metric": "Mcell-RHS evals/s + SDC steps/s (FP64, 1 MI355X); achieved HBM GB/s vs peak",
+        "value": steps_per_s,
+        "unit": "SDC steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": ncell, "species": ns, "reactions": int(mech["nr"]),
+                   "scheme": sch_d, "dt": dt},
+        "mcell_ad_evals_per_s": ncell * n_ad / el / 1e6,
+        "mcell_r_evals_per_s": ncell * n_r / el / 1e6,
+        "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, mech, ncell)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/* narrowsdc: right-hand side of the multicomponent reacting compressible
+ * Navier-Stokes equations on periodic 3D boxes and its (multirate) spectral
+ * deferred correction step, in FP64 on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Emmett, Zhang & Bell, "High-order algorithms for compressible
+ * reacting flow with complex chemistry" (arXiv 1309.7327).
+ *   - state vector and equations: Section 2.1, eq. (cns)
+ *   - eighth-order centred first derivative, eighth-order narrow stencil for
+ *     d/dx(a du/dx): Section 2.2, eqs. (DaDu), (H) and the 8x8 matrix M
+ *   - correction-velocity species fluxes with the chain rule: Section 2.1
+ *     eqs. (fbar), (Vc) and Section 2.4
+ *   - SDC sweep: Section 3.1, eq. (expsdc); MRSDC mode 1: Section 3.2,
+ *     eq. (mrupdate)
+ *
+ * Conventions for every entry point
+ *   - Fields are FP64, component-major, x fastest: field[q][z][y][x].
+ *     "Ghosted" arrays have NG = 4 ghost layers on every side (as the paper's
+ *     q, D arrays of Listing 1), i.e. (nx+8)*(ny+8)*(nz+8) cells per
+ *     component; "interior" arrays have nx*ny*nz cells per component.
+ *   - State vector U = (rho, rho u, rho v, rho w, rho E, rho Y_1 .. rho Y_ns),
+ *     nU = 5 + ns components, SI units.
+ *   - All field pointers are device pointers owned by the caller, 8-byte
+ *     aligned, not aliasing each other unless stated.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream) and returns after argument checks with one of the status codes
+ *     below.  Failures detected on the device (temperature Newton solve not
+ *     converged, temperature outside the polynomial range, non-positive
+ *     density) set a per-context error word that last_status() returns.
+ *   - A context is used from one host thread at a time.
+ */
+#ifndef NARROWSDC_H
+#define NARROWSDC_H
+#include <stddef.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SDC_OK = 0,
+  SDC_EINVAL = -1,      /* bad argument (null pointer, size, unsupported ns) */
+  SDC_ENOMECH = -2,     /* no mechanism set on the context */
+  SDC_EHIP = -3,        /* HIP runtime error */
+  SDC_ETEMP = -4,       /* device: temperature solve failed / out of range / rho <= 0 */
+  SDC_ENOMEM = -5,      /* workspace too small or allocation failed */
+};
+
+/* parts of the right-hand side (rhs_eval): convective terms, diffusive
+ * terms (viscous, conductive, species diffusion), chemistry source */
+enum { RHS_HYP = 1, RHS_DIFF = 2, RHS_REACT = 4, RHS_AD = 3, RHS_ALL = 7 };
+
+typedef struct sdc_context sdc_context;
+
+typedef struct {
+  int nx, ny, nz;     /* interior cells, each >= 1 */
+  int ng;             /* ghost layers: must be 4 */
+  double dx, dy, dz;  /* grid spacing, m */
+} box_desc;
+
+/* Chemical mechanism and transport model (host pointers, deep-copied by
+ * set_mechanism).  Thermodynamics: single-range NASA-7 polynomials,
+ * c_p/R = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4, enthalpy constant a6,
+ * entropy constant a7, valid on [Tlo, Thi].  Reactions: reversible,
+ * k_f = A T^b exp(-Ea/(R T)), reverse constant from the equilibrium
+ * constant of the NASA Gibbs energies at p_ref = 101325 Pa; at most two
+ * reactant and two product molecules per reaction (coefficients 0..2).
+ * Transport: mu = mu_ref (T/T_ref)^mu_exp, lambda = mu c_p / Pr,
+ * rho D_k = lambda / (c_p Le_k), bulk viscosity xi = bulk_ratio * mu.
+ * m47, m48: the two free parameters of the eighth-order narrow stencil. */
+typedef struct {
+  int ns, nr;            /* species (9 or 21 supported), reactions (<= 256) */
+  const double *W;       /* [ns] molecular weights, kg/mol */
+  const double *nasa;    /* [ns][7] */
+  double Tlo, Thi;
+  const double *A;       /* [nr] SI units of the forward order */
+  const double *b;       /* [nr] */
+  const double *Ea;      /* [nr] J/mol */
+  const int *nu_f;       /* [nr][ns] reactant coefficients */
+  const int *nu_r;       /* [nr][ns] product coefficients */
+  const double *Le;      /* [ns] Lewis numbers */
+  double mu_ref, T_ref, mu_exp, Pr, bulk_ratio;
+  double m47, m48;
+} mechanism_desc;
+
+/* Time scheme.  n_fine == 0: single-rate SDC (eq. expsdc) on n_coarse
+ * Gauss-Lobatto nodes with the full right-hand side.  n_fine >= 2: MRSDC
+ * mode 1 (eq. mrupdate): advection-diffusion on the n_coarse Gauss-Lobatto
+ * nodes, chemistry on n_fine Gauss-Lobatto nodes repeated fine_repeat times
+ * inside every coarse interval (fine_repeat = 1: type (b); > 1: type (c)). */
+typedef struct {
+  int n_coarse;     /* 2..8 */
+  int sweeps;       /* K >= 1 */
+  int n_fine;       /* 0 or 2..9 */
+  int fine_repeat;  /* >= 1 */
+} sdc_scheme;
+
+/* Create a context on HIP device `device`.  Owns the device copy of the
+ * mechanism, scratch for rhs_eval (grown on demand with hipMalloc) and the
+ * device error word. */
+int sdc_context_create(sdc_context **out, int device);
+int sdc_context_destroy(sdc_context *ctx);
+
+/* Copy a mechanism to the device (synchronous).  Returns SDC_EINVAL for
+ * unsupported sizes or reactions with more than two molecules per side. */
+int set_mechanism(sdc_context *ctx, const mechanism_desc *mech);
+
+/* Conserved state from primitives on the interior: p, T [nz][ny][nx],
+ * Y [ns][nz][ny][nx], u [3][nz][ny][nx] (device, interior layout) -> U
+ * (device, ghosted; ghost layers filled periodically).  Ideal-gas mixture:
+ * rho = p Wbar/(R T), rho E = rho (e(T, Y) + |u|^2/2) (Section 2.1). */
+int prim_to_cons(sdc_context *ctx, const box_desc *box, const double *p, const double *T,
+                 const double *Y, const double *u, double *U, void *stream);
+
+/* Right-hand side dU/dt of eq. (cns) on the interior.
+ * U: ghosted state; its ghost layers are overwritten by the periodic fill.
+ * dUdt: interior, nU components, overwritten.  parts: RHS_* mask.
+ * Uses context scratch (allocated on first use or growth). */
+int rhs_eval(sdc_context *ctx, const box_desc *box, double *U, double *dUdt, unsigned parts,
+             void *stream);
+
+/* Bytes of device workspace sdc_step / sdc_step_batched need. */
+int sdc_workspace_size(const sdc_context *ctx, int nbox, const box_desc *boxes,
+                       const sdc_scheme *scheme, size_t *bytes);
+
+/* Advance U (ghosted, in place) by nsteps steps of size dt with the scheme.
+ * f(U_0) is recycled across the steps of one call.  workspace: caller-owned
+ * device memory of at least sdc_workspace_size bytes; nothing is allocated. */
+int sdc_step(sdc_context *ctx, const box_desc *box, double *U, double dt, int nsteps,
+             const sdc_scheme *scheme, void *workspace, size_t ws_bytes, void *stream);
+
+/* Same for nbox independent periodic boxes advanced together: every stage
+ * is one launch over a (box, tile) work list covering all boxes.
+ * U[i] is box i's ghosted state (device pointer, host array of pointers). */
+int sdc_step_batched(sdc_context *ctx, int nbox, const box_desc *boxes, double *const *U,
+                     double dt, int nsteps, const sdc_scheme *scheme, void *workspace,
+                     size_t ws_bytes, void *stream);
+
+/* Synchronise `stream`, return and clear the device error word (SDC_OK or
+ * SDC_ETEMP). */
+int last_status(sdc_context *ctx, void *stream);
+
+/* Text of the last error returned by a call on this context. */
+const char *last_error_message(const sdc_context *ctx);
+
+/* ---- measurement and tuning hooks ------------------------------------
+ * sdc_profile_enable: attach (1, clearing previous records) or detach (0)
+ *   per-kernel timers; while attached every launch is bracketed by HIP
+ *   events recorded on its own stream.
+ * sdc_profile_read: synchronise `stream`, write the summed duration (ms)
+ *   and launch count of every kernel kind into total_ms[], count[] (arrays of
+ *   at least 16 entries), clear the records; returns the number of kinds.
+ * sdc_kernel_name: name of kernel kind `id` ("" if out of range).
+ * sdc_set_tiles: force the tile shapes (threads x, y, z; product <= 256) of
+ *   the interior and stored index spaces (0 = automatic) and cap the number
+ *   of workgroups per launch (0 = one per work item). */
+int sdc_profile_enable(sdc_context *ctx, int enable);
+int sdc_profile_read(sdc_context *ctx, void *stream, double *total_ms, int *count);
+const char *sdc_kernel_name(int id);
+int sdc_set_tiles(sdc_context *ctx, int ix, int iy, int iz, int sx, int sy, int sz, int grid_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

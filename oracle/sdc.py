@@ -99,9 +99,11 @@ class Counter:
         return self.f(U, t)
 
 
-def sdc_run(f, U0, t0, dt, nodes, K, nsteps):
+def sdc_run(f, U0, t0, dt, nodes, K, nsteps, perturb=None):
     """Single-rate SDC: nsteps steps of K sweeps each (eq. expsdc).
-    f(U, t) -> dU/dt.  Returns the final state."""
+    f(U, t) -> dU/dt.  Returns the final state.  perturb (optional) is
+    applied to every new node state (used to measure rounding sensitivity)."""
+    perturb = perturb or (lambda U: U)
     M = len(nodes) - 1
     S = s_matrix(nodes)
     dtau = np.diff(nodes) * dt
@@ -119,17 +121,18 @@ def sdc_run(f, U0, t0, dt, nodes, K, nsteps):
                 if m > 0:
                     Fn.append(f(Un[m], times[m]))
                 SF = sum(S[m, j] * Fk[j] for j in range(M + 1))
-                Un.append(Un[m] + dtau[m] * (Fn[m] - Fk[m]) + dt * SF)
+                Un.append(perturb(Un[m] + dtau[m] * (Fn[m] - Fk[m]) + dt * SF))
             Fn.append(f(Un[M], times[M]))
             Uk, Fk = Un, Fn
         U0, F0 = Uk[M], Fk[M]
     return U0
 
 
-def mrsdc_run(f1, f2, U0, t0, dt, t1, t2, pieces, K, nsteps):
+def mrsdc_run(f1, f2, U0, t0, dt, t1, t2, pieces, K, nsteps, perturb=None):
     """Multirate SDC, mode 1 (eq. mrupdate): explicit forward-Euler corrections
     of both components on the fine nodes, f1 frozen at the coarse node to the
-    left.  Returns the final state."""
+    left.  Returns the final state.  perturb as in sdc_run."""
+    perturb = perturb or (lambda U: U)
     M1, M2 = len(t1) - 1, len(t2) - 1
     r = M2 // M1
     assert r * M1 == M2
@@ -154,7 +157,7 @@ def mrsdc_run(f1, f2, U0, t0, dt, t1, t2, pieces, K, nsteps):
                         F1n[p] = f1(U, tn + t1[p] * dt)
                 S = sum(S22[q, j] * F2k[j] for j in range(M2 + 1)) + \
                     sum(S21[q, j] * F1k[j] for j in range(M1 + 1))
-                U = U + dtq[q] * (F1n[p] - F1k[p]) + dtq[q] * (F2n[q] - F2k[q]) + dt * S
+                U = perturb(U + dtq[q] * (F1n[p] - F1k[p]) + dtq[q] * (F2n[q] - F2k[q]) + dt * S)
             F2n[M2] = f2(U, tn + dt)
             F1n[M1] = f1(U, tn + dt)
             F1k, F2k = F1n, F2n

@@ -1,0 +1,852 @@
+// C-ABI of the narrowsdc library: context, mechanism upload, work plans,
+// right-hand-side evaluation and the (multirate) SDC drivers.
+//
+// The time integrators follow Section 3 of the paper: collocation on
+// Gauss-Lobatto nodes with node-to-node integration matrices S built from
+// exact integrals of the Lagrange basis (eqs. gaussapp, compact, expsdc);
+// MRSDC mode 1 with the coarse term frozen at the coarse node to the left of
+// each fine node (eq. mrupdate) and piecewise-polynomial fine integration
+// matrices for fine nodes of type (b)/(c).  f(U_0) is recycled across the
+// steps of one call.
+#include "../../include/narrowsdc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "nsdc_internal.h"
+
+using namespace nsdc;
+
+namespace {
+
+constexpr double RU = 8.31446261815324;
+
+// ------------------------------------------------------------- quadrature
+// Legendre polynomial P_n and its derivative at x (three-term recurrence).
+void legendre(int n, long double x, long double &p, long double &dp) {
+  long double p0 = 1.0L, p1 = x;
+  if (n == 0) { p = 1.0L; dp = 0.0L; return; }
+  for (int k = 2; k <= n; ++k) {
+    long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = n * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+// Gauss-Lobatto nodes on [0, 1]: 0, 1 and the roots of P'_{n-1} (Newton from
+// the Chebyshev-Lobatto points).
+std::vector<long double> gauss_lobatto(int n) {
+  std::vector<long double> x(n);
+  const int N = n - 1;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < n; ++j) {
+    long double t = -std::cos(pi * j / N);
+    if (j > 0 && j < N) {
+      for (int it = 0; it < 100; ++it) {
+        // f = P'_N, f' from the Legendre equation: (1-t^2) P''_N = 2t P'_N - N(N+1) P_N
+        long double p, dp;
+        legendre(N, t, p, dp);
+        long double ddp = (2 * t * dp - N * (N + 1) * p) / (1 - t * t);
+        long double dx = dp / ddp;
+        t -= dx;
+        if (std::fabs((double)dx) < 1e-19) break;
+      }
+    }
+    x[j] = 0.5L * (t + 1.0L);
+  }
+  x[0] = 0.0L;
+  x[N] = 1.0L;
+  return x;
+}
+
+// Gauss-Legendre rule with n points on [-1, 1] (Newton on P_n).
+void gauss_legendre(int n, std::vector<long double> &x, std::vector<long double> &w) {
+  x.resize(n);
+  w.resize(n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    long double t = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    long double p, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, t, p, dp);
+      long double dx = p / dp;
+      t -= dx;
+      if (std::fabs((double)dx) < 1e-19) break;
+    }
+    legendre(n, t, p, dp);
+    x[i] = t;
+    w[i] = 2.0L / ((1 - t * t) * dp * dp);
+  }
+}
+
+// integral over [a, b] of the Lagrange basis polynomial j of `nodes`
+long double lagrange_integral(const std::vector<long double> &nodes, int j, long double a,
+                              long double b) {
+  std::vector<long double> gx, gw;
+  gauss_legendre((int)nodes.size(), gx, gw);
+  long double sum = 0.0L;
+  for (size_t q = 0; q < gx.size(); ++q) {
+    long double t = 0.5L * (a + b) + 0.5L * (b - a) * gx[q];
+    long double l = 1.0L;
+    for (size_t i = 0; i < nodes.size(); ++i)
+      if ((int)i != j) l *= (t - nodes[i]) / (nodes[j] - nodes[i]);
+    sum += gw[q] * l;
+  }
+  return 0.5L * (b - a) * sum;
+}
+
+// ------------------------------------------------------------ plans
+struct Plan {
+  std::vector<box_desc> boxes;
+  int nbox = 0;
+  long long totS = 0, totI = 0;
+  BoxDev *d_boxes = nullptr;
+  Item *d_items = nullptr;   // interior, stored, ghost lists back to back
+  int nI = 0, nS = 0, nG = 0;
+  TileShape tsI{}, tsS{};
+  double **d_Utab = nullptr;
+  std::vector<double *> Uptrs;
+  ~Plan() {
+    if (d_boxes) (void)hipFree(d_boxes);
+    if (d_items) (void)hipFree(d_items);
+    if (d_Utab) (void)hipFree(d_Utab);
+  }
+};
+
+TileShape default_tile(int nx, int ny, int nz) {
+  (void)ny;
+  (void)nz;
+  if (nx >= 64) return TileShape{64, 4, 1};
+  if (nx >= 32) return TileShape{32, 8, 1};
+  return TileShape{16, 4, 4};
+}
+
+std::string plan_key(int nbox, const box_desc *b, double *const *U, TileShape tI, TileShape tS) {
+  std::string k;
+  k.reserve(64 * nbox + 64);
+  char buf[160];
+  snprintf(buf, sizeof buf, "n%d|%d,%d,%d|%d,%d,%d|", nbox, tI.tx, tI.ty, tI.tz, tS.tx, tS.ty, tS.tz);
+  k += buf;
+  for (int i = 0; i < nbox; ++i) {
+    snprintf(buf, sizeof buf, "%d,%d,%d,%.17g,%.17g,%.17g,%p;", b[i].nx, b[i].ny, b[i].nz, b[i].dx,
+             b[i].dy, b[i].dz, U ? (void *)U[i] : nullptr);
+    k += buf;
+  }
+  return k;
+}
+
+}  // namespace
+
+// Per-kernel HIP-event timers: events are recorded on the launch stream
+// around every launch while a profiler is attached to the context.
+namespace nsdc {
+struct Profiler {
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used < pool.size()) return pool[used++];
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+    ++used;
+    return e;
+  }
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+void prof_begin(Profiler *p, int id, hipStream_t s) {
+  if (!p) return;
+  hipEvent_t e = p->get();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  p->recs.push_back(Profiler::Rec{id, e, nullptr});
+}
+void prof_end(Profiler *p, int id, hipStream_t s) {
+  (void)id;
+  if (!p || p->recs.empty() || p->recs.back().b) return;
+  hipEvent_t e = p->get();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  p->recs.back().b = e;
+}
+}  // namespace nsdc
+
+static const char *KERNEL_NAMES[K_NKERNELS] = {"prim_to_cons", "ghost", "prims", "vgrad", "dir_x",
+                                               "dir_y", "dir_z", "chem", "sdc_node", "mr_fine"};
+
+struct sdc_context {
+  int device = 0;
+  bool has_mech = false;
+  DevMech h_mech{};
+  DevMech *d_mech = nullptr;
+  const Ops *ops = nullptr;
+  int *d_err = nullptr;
+  std::string msg;
+  // rhs_eval scratch
+  double *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  // multirate coefficient tables, keyed by scheme
+  FineCoef *d_fine = nullptr;
+  std::string fine_key;
+  std::map<std::string, std::unique_ptr<Plan>> plans;
+  TileShape forceI{0, 0, 0}, forceS{0, 0, 0};
+  int grid_cap = 0;
+  std::unique_ptr<Profiler> prof;
+};
+
+namespace {
+
+int fail(sdc_context *c, int code, const std::string &m) {
+  if (c) c->msg = m;
+  return code;
+}
+
+#define HIPCHECK(ctx, expr)                                                                 \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, SDC_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int check_box(sdc_context *c, const box_desc *b) {
+  if (!b) return fail(c, SDC_EINVAL, "null box");
+  if (b->nx < 1 || b->ny < 1 || b->nz < 1) return fail(c, SDC_EINVAL, "box extents must be >= 1");
+  if (b->ng != NSDC_NG) return fail(c, SDC_EINVAL, "ghost layers must be 4");
+  if (!(b->dx > 0) || !(b->dy > 0) || !(b->dz > 0)) return fail(c, SDC_EINVAL, "grid spacing must be > 0");
+  const long long s = (long long)(b->nx + 8) * (b->ny + 8) * (b->nz + 8);
+  if (s > (1LL << 31)) return fail(c, SDC_EINVAL, "box too large");
+  return SDC_OK;
+}
+
+// Build (or fetch) the work plan of a set of boxes.
+int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Plan **out) {
+  TileShape tI{}, tS{};
+  if (c->forceI.tx) {
+    tI = c->forceI;
+    tS = c->forceS;
+  } else {
+    int mx = 0, my = 0, mz = 0;
+    for (int i = 0; i < nbox; ++i) {
+      mx = std::max(mx, bx[i].nx);
+      my = std::max(my, bx[i].ny);
+      mz = std::max(mz, bx[i].nz);
+    }
+    if (nbox > 1) mx = 16;   // batches: one tile shape for every box
+    tI = default_tile(mx, my, mz);
+    tS = default_tile(nbox > 1 ? 16 : mx + 8, my + 8, mz + 8);
+  }
+  std::string key = plan_key(nbox, bx, U, tI, tS);
+  auto it = c->plans.find(key);
+  if (it != c->plans.end()) {
+    *out = it->second.get();
+    return SDC_OK;
+  }
+  if (c->plans.size() > 32) c->plans.clear();
+  auto p = std::make_unique<Plan>();
+  p->nbox = nbox;
+  p->boxes.assign(bx, bx + nbox);
+  p->tsI = tI;
+  p->tsS = tS;
+  std::vector<BoxDev> hb(nbox);
+  std::vector<Item> iI, iS, iG;
+  for (int b = 0; b < nbox; ++b) {
+    BoxDev &d = hb[b];
+    d.nx = bx[b].nx; d.ny = bx[b].ny; d.nz = bx[b].nz;
+    d.sx = d.nx + 2 * NSDC_NG; d.sy = d.ny + 2 * NSDC_NG; d.sz = d.nz + 2 * NSDC_NG;
+    d.offS = p->totS;
+    d.offI = p->totI;
+    const double h[3] = {bx[b].dx, bx[b].dy, bx[b].dz};
+    for (int k = 0; k < 3; ++k) {
+      d.idx[k] = 1.0 / h[k];
+      d.idx2[k] = 1.0 / (h[k] * h[k]);
+    }
+    p->totS += (long long)d.sx * d.sy * d.sz;
+    p->totI += (long long)d.nx * d.ny * d.nz;
+    for (int z = 0; z < d.nz; z += tI.tz)
+      for (int y = 0; y < d.ny; y += tI.ty)
+        for (int x = 0; x < d.nx; x += tI.tx) iI.push_back(Item{b, x, y, z});
+    for (int z = 0; z < d.sz; z += tS.tz)
+      for (int y = 0; y < d.sy; y += tS.ty)
+        for (int x = 0; x < d.sx; x += tS.tx) iS.push_back(Item{b, x, y, z});
+    const long long ng = (long long)d.sx * d.sy * d.sz - (long long)d.nx * d.ny * d.nz;
+    for (long long g = 0; g < ng; g += 256) iG.push_back(Item{b, (int)g, 0, 0});
+  }
+  p->nI = (int)iI.size();
+  p->nS = (int)iS.size();
+  p->nG = (int)iG.size();
+  std::vector<Item> all;
+  all.insert(all.end(), iI.begin(), iI.end());
+  all.insert(all.end(), iS.begin(), iS.end());
+  all.insert(all.end(), iG.begin(), iG.end());
+  HIPCHECK(c, hipMalloc(&p->d_boxes, sizeof(BoxDev) * nbox));
+  HIPCHECK(c, hipMemcpy(p->d_boxes, hb.data(), sizeof(BoxDev) * nbox, hipMemcpyHostToDevice));
+  HIPCHECK(c, hipMalloc(&p->d_items, sizeof(Item) * all.size()));
+  HIPCHECK(c, hipMemcpy(p->d_items, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice));
+  if (U) {
+    p->Uptrs.assign(U, U + nbox);
+    HIPCHECK(c, hipMalloc(&p->d_Utab, sizeof(double *) * nbox));
+    HIPCHECK(c, hipMemcpy(p->d_Utab, U, sizeof(double *) * nbox, hipMemcpyHostToDevice));
+  }
+  *out = p.get();
+  c->plans[key] = std::move(p);
+  return SDC_OK;
+}
+
+LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
+  LaunchCtx l;
+  l.stream = s;
+  l.boxes = p->d_boxes;
+  l.itemsI = p->d_items;
+  l.itemsS = p->d_items + p->nI;
+  l.itemsG = p->d_items + p->nI + p->nS;
+  l.nI = p->nI;
+  l.nS = p->nS;
+  l.nG = p->nG;
+  l.tsI = p->tsI;
+  l.tsS = p->tsS;
+  l.cap = c->grid_cap > 0 ? c->grid_cap : 1 << 30;
+  l.mech = c->d_mech;
+  l.err = c->d_err;
+  l.prof = c->prof.get();
+  return l;
+}
+
+// One right-hand-side evaluation into F (interior) from U (ghosted).
+void eval_rhs_g(const Ops *o, const LaunchCtx &l, FRef U, double *P, double *G, FRef F, unsigned parts) {
+  o->ghost(l, U);
+  o->prims(l, U, P, F, (parts & RHS_REACT) ? 2 : 1);
+  if (parts & RHS_DIFF) o->vgrad(l, P, G);
+  if (parts & RHS_AD) {
+    for (int d = 0; d < 3; ++d) o->dir(l, d, U, P, G, F, parts & RHS_AD);
+  }
+}
+
+int check_scheme(sdc_context *c, const sdc_scheme *s) {
+  if (!s) return fail(c, SDC_EINVAL, "null scheme");
+  if (s->n_coarse < 2 || s->n_coarse > 8) return fail(c, SDC_EINVAL, "n_coarse must be in 2..8");
+  if (s->sweeps < 1) return fail(c, SDC_EINVAL, "sweeps must be >= 1");
+  if (s->n_fine != 0) {
+    if (s->n_fine < 2 || s->n_fine > 9 || s->fine_repeat < 1)
+      return fail(c, SDC_EINVAL, "n_fine must be 0 or in 2..9, fine_repeat >= 1");
+    if ((s->n_fine - 1) * s->fine_repeat > NSDC_MAXFINE - 1)
+      return fail(c, SDC_EINVAL, "too many fine sub-steps per coarse interval");
+  }
+  return SDC_OK;
+}
+
+// workspace layout (doubles), in order: P, G, U buffers, F arrays
+struct WsLayout {
+  size_t P, G, Ub, F1, F2, total;
+  int nUb, nF1, nF2;
+};
+
+WsLayout ws_layout(const Plan *p, int ns, const sdc_scheme *s) {
+  WsLayout w{};
+  const int nU = 5 + ns, nP = 8 + 3 * ns;
+  const int M1 = s->n_coarse - 1;
+  const bool mr = s->n_fine != 0;
+  const int M2 = mr ? M1 * (s->n_fine - 1) * s->fine_repeat : 0;
+  w.nUb = mr ? 1 : 2;
+  w.nF1 = 1 + 2 * M1;
+  w.nF2 = mr ? 1 + 2 * M2 : 0;
+  size_t off = 0;
+  auto take = [&](size_t n) { size_t o = off; off += (n + 31) & ~size_t(31); return o; };
+  w.P = take((size_t)p->totS * nP);
+  w.G = take((size_t)p->totS * 9);
+  w.Ub = take((size_t)p->totS * nU * w.nUb);
+  w.F1 = take((size_t)p->totI * nU * w.nF1);
+  w.F2 = take((size_t)p->totI * ns * w.nF2);
+  w.total = off;
+  return w;
+}
+
+// multirate coefficient tables for the scheme, uploaded once per scheme
+int fine_tables(sdc_context *c, const sdc_scheme *s) {
+  char key[64];
+  snprintf(key, sizeof key, "%d,%d,%d", s->n_coarse, s->n_fine, s->fine_repeat);
+  if (c->d_fine && c->fine_key == key) return SDC_OK;
+  const int M1 = s->n_coarse - 1;
+  const int r = (s->n_fine - 1) * s->fine_repeat;
+  std::vector<long double> t1 = gauss_lobatto(s->n_coarse), g = gauss_lobatto(s->n_fine);
+  std::vector<FineCoef> fc(M1);
+  for (int p = 0; p < M1; ++p) {
+    FineCoef &f = fc[p];
+    std::memset(&f, 0, sizeof f);
+    f.n1 = M1 + 1;
+    f.nq = r;
+    // fine nodes of this coarse interval: `repeat` copies of the fine rule
+    std::vector<long double> tf(r + 1);
+    const long double a = t1[p], b = t1[p + 1];
+    for (int rep = 0; rep < s->fine_repeat; ++rep) {
+      const long double lo = a + (b - a) * rep / s->fine_repeat;
+      const long double hi = a + (b - a) * (rep + 1) / s->fine_repeat;
+      for (int j = 0; j < s->n_fine; ++j) tf[rep * (s->n_fine - 1) + j] = lo + (hi - lo) * g[j];
+    }
+    tf[r] = b;
+    for (int q = 0; q < r; ++q) {
+      f.dtq[q] = (double)(tf[q + 1] - tf[q]);
+      for (int j = 0; j <= M1; ++j) f.S21[q][j] = (double)lagrange_integral(t1, j, tf[q], tf[q + 1]);
+      // piece of the fine interpolant containing [t_q, t_{q+1}]
+      const int piece = q / (s->n_fine - 1);
+      std::vector<long double> loc(tf.begin() + piece * (s->n_fine - 1),
+                                   tf.begin() + piece * (s->n_fine - 1) + s->n_fine);
+      for (int j = 0; j < s->n_fine; ++j)
+        f.S22[q][piece * (s->n_fine - 1) + j] = (double)lagrange_integral(loc, j, tf[q], tf[q + 1]);
+    }
+  }
+  if (c->d_fine) (void)hipFree(c->d_fine);
+  c->d_fine = nullptr;
+  HIPCHECK(c, hipMalloc(&c->d_fine, sizeof(FineCoef) * M1));
+  HIPCHECK(c, hipMemcpy(c->d_fine, fc.data(), sizeof(FineCoef) * M1, hipMemcpyHostToDevice));
+  c->fine_key = key;
+  return SDC_OK;
+}
+
+int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sdc_scheme *s,
+            void *ws, size_t ws_bytes, hipStream_t st) {
+  const Ops *o = c->ops;
+  const int ns = o->ns, nU = 5 + ns;
+  const WsLayout L = ws_layout(p, ns, s);
+  if (!ws) return fail(c, SDC_EINVAL, "null workspace");
+  if (ws_bytes < L.total * sizeof(double)) return fail(c, SDC_ENOMEM, "workspace too small");
+  double *W = (double *)ws;
+  double *P = W + L.P, *G = W + L.G;
+  const LaunchCtx l = make_lc(c, p, st);
+  const long long fI = p->totI * nU, fS = p->totS * nU;
+  const int M = s->n_coarse - 1, K = s->sweeps;
+  std::vector<long double> t = gauss_lobatto(s->n_coarse);
+  if (s->n_fine == 0) {
+    // ---------------------------------------------- single-rate SDC
+    double Sm[8][8] = {}, dtau[8] = {};
+    for (int m = 0; m < M; ++m) {
+      dtau[m] = (double)(t[m + 1] - t[m]);
+      for (int j = 0; j <= M; ++j) Sm[m][j] = (double)lagrange_integral(t, j, t[m], t[m + 1]);
+    }
+    double *F0 = W + L.F1;
+    double *FA[8], *FB[8];
+    for (int m = 1; m <= M; ++m) {
+      FA[m] = W + L.F1 + fI * m;
+      FB[m] = W + L.F1 + fI * (M + m);
+    }
+    FRef Ub[2] = {FRef{W + L.Ub, nullptr}, FRef{W + L.Ub + fS, nullptr}};
+    eval_rhs_g(o, l, Uuser, P, G, FRef{F0, nullptr}, RHS_ALL);
+    for (int step = 0; step < nsteps; ++step) {
+      const double *Fold[8];
+      for (int j = 0; j <= M; ++j) Fold[j] = F0;
+      double *Fnew[8];
+      for (int k = 0; k < K; ++k) {
+        Fnew[0] = F0;
+        for (int m = 1; m <= M; ++m) Fnew[m] = (k % 2 == 0) ? FA[m] : FB[m];
+        FRef Ucur = Uuser;
+        for (int m = 0; m < M; ++m) {
+          if (m > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL);
+          FRef Unext = (m == M - 1 && k == K - 1) ? Uuser : Ub[m % 2];
+          NodeArgs a{};
+          for (int j = 0; j <= M; ++j) {
+            a.Fold[j] = Fold[j];
+            a.S[j] = Sm[m][j];
+          }
+          a.nnodes = M + 1;
+          a.Fnew_m = Fnew[m];
+          a.Fold_m = Fold[m];
+          a.dtau = dtau[m] * dt;
+          a.dt = dt;
+          o->sdc_node(l, Ucur, Unext, a);
+          Ucur = Unext;
+        }
+        const bool last = step == nsteps - 1 && k == K - 1;
+        if (!last) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL);
+        for (int j = 0; j <= M; ++j) Fold[j] = Fnew[j];
+      }
+      if (step < nsteps - 1) {
+        // recycle f(U_M) as the next step's f(U_0): exchange array roles
+        double *fin = Fnew[M];
+        double *old0 = F0;
+        F0 = fin;
+        for (int m = 1; m <= M; ++m) {
+          if (FA[m] == fin) FA[m] = old0;
+          if (FB[m] == fin) FB[m] = old0;
+        }
+      }
+    }
+    o->ghost(l, Uuser);
+    return SDC_OK;
+  }
+  // ------------------------------------------------ multirate SDC, mode 1
+  int rc = fine_tables(c, s);
+  if (rc) return rc;
+  const int r = (s->n_fine - 1) * s->fine_repeat;
+  const int M2 = M * r;
+  const long long f2I = p->totI * ns;
+  double *F10 = W + L.F1, *F20 = W + L.F2;
+  std::vector<double *> F1A(M + 1), F1B(M + 1), F2A(M2 + 1), F2B(M2 + 1);
+  for (int m = 1; m <= M; ++m) {
+    F1A[m] = W + L.F1 + fI * m;
+    F1B[m] = W + L.F1 + fI * (M + m);
+  }
+  for (int q = 1; q <= M2; ++q) {
+    F2A[q] = W + L.F2 + f2I * q;
+    F2B[q] = W + L.F2 + f2I * (M2 + q);
+  }
+  FRef Ucur{W + L.Ub, nullptr};
+  eval_rhs_g(o, l, Uuser, P, G, FRef{F10, nullptr}, RHS_AD);
+  o->chem(l, Uuser, F20);
+  std::vector<const double *> F1old(M + 1), F2old(M2 + 1);
+  std::vector<double *> F1new(M + 1), F2new(M2 + 1);
+  for (int step = 0; step < nsteps; ++step) {
+    for (int j = 0; j <= M; ++j) F1old[j] = F10;
+    for (int q = 0; q <= M2; ++q) F2old[q] = F20;
+    for (int k = 0; k < K; ++k) {
+      F1new[0] = F10;
+      F2new[0] = F20;
+      for (int m = 1; m <= M; ++m) F1new[m] = (k % 2 == 0) ? F1A[m] : F1B[m];
+      for (int q = 1; q <= M2; ++q) F2new[q] = (k % 2 == 0) ? F2A[q] : F2B[q];
+      const bool last = step == nsteps - 1 && k == K - 1;
+      FRef Uout = Ucur;
+      for (int pi = 0; pi < M; ++pi) {
+        FRef Uin = pi == 0 ? Uuser : Ucur;
+        if (pi > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{F1new[pi], nullptr}, RHS_AD);
+        Uout = (k == K - 1 && pi == M - 1) ? Uuser : Ucur;
+        FinePtrs fp{};
+        for (int j = 0; j <= M; ++j) fp.F1old[j] = F1old[j];
+        fp.F1new_p = F1new[pi];
+        fp.F1old_p = F1old[pi];
+        for (int j = 0; j <= r; ++j) {
+          fp.F2old[j] = F2old[pi * r + j];
+          fp.F2new[j] = F2new[pi * r + j];
+        }
+        fp.q0_known = pi == 0;
+        fp.eval_last = (pi == M - 1) && !last;
+        fp.dt = dt;
+        o->mr_fine(l, Uin, Uout, c->d_fine + pi, fp);
+      }
+      if (!last) eval_rhs_g(o, l, Uout, P, G, FRef{F1new[M], nullptr}, RHS_AD);
+      for (int j = 0; j <= M; ++j) F1old[j] = F1new[j];
+      for (int q = 0; q <= M2; ++q) F2old[q] = F2new[q];
+    }
+    if (step < nsteps - 1) {
+      double *fin1 = F1new[M], *fin2 = F2new[M2];
+      double *o1 = F10, *o2 = F20;
+      F10 = fin1;
+      F20 = fin2;
+      for (int m = 1; m <= M; ++m) {
+        if (F1A[m] == fin1) F1A[m] = o1;
+        if (F1B[m] == fin1) F1B[m] = o1;
+      }
+      for (int q = 1; q <= M2; ++q) {
+        if (F2A[q] == fin2) F2A[q] = o2;
+        if (F2B[q] == fin2) F2B[q] = o2;
+      }
+    }
+  }
+  o->ghost(l, Uuser);
+  return SDC_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+int sdc_context_create(sdc_context **out, int device) {
+  if (!out) return SDC_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SDC_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return SDC_EHIP;
+  auto *c = new sdc_context();
+  c->device = device;
+  if (hipMalloc(&c->d_err, sizeof(int)) != hipSuccess || hipMemset(c->d_err, 0, sizeof(int)) != hipSuccess ||
+      hipMalloc(&c->d_mech, sizeof(DevMech)) != hipSuccess) {
+    delete c;
+    return SDC_EHIP;
+  }
+  *out = c;
+  return SDC_OK;
+}
+
+int sdc_context_destroy(sdc_context *c) {
+  if (!c) return SDC_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->plans.clear();
+  if (c->d_err) (void)hipFree(c->d_err);
+  if (c->d_mech) (void)hipFree(c->d_mech);
+  if (c->scratch) (void)hipFree(c->scratch);
+  if (c->d_fine) (void)hipFree(c->d_fine);
+  delete c;
+  return SDC_OK;
+}
+
+int set_mechanism(sdc_context *c, const mechanism_desc *m) {
+  if (!c || !m) return fail(c, SDC_EINVAL, "null argument");
+  const Ops *o = ops_for(m->ns);
+  if (!o) return fail(c, SDC_EINVAL, "unsupported species count (9 or 21)");
+  if (m->nr < 0 || m->nr > NSDC_NRMAX) return fail(c, SDC_EINVAL, "too many reactions");
+  if (!m->W || !m->nasa || !m->Le || (m->nr > 0 && (!m->A || !m->b || !m->Ea || !m->nu_f || !m->nu_r)))
+    return fail(c, SDC_EINVAL, "null mechanism array");
+  if (!(m->Tlo > 0) || !(m->Thi > m->Tlo)) return fail(c, SDC_EINVAL, "bad temperature range");
+  DevMech &d = c->h_mech;
+  std::memset(&d, 0, sizeof d);
+  d.ns = m->ns;
+  d.nr = m->nr;
+  d.Tlo = m->Tlo;
+  d.Thi = m->Thi;
+  d.mu_ref = m->mu_ref;
+  d.inv_Tref = 1.0 / m->T_ref;
+  d.mu_exp = m->mu_exp;
+  d.inv_Pr = 1.0 / m->Pr;
+  d.bulk = m->bulk_ratio;
+  for (int k = 0; k < m->ns; ++k) {
+    if (!(m->W[k] > 0) || !(m->Le[k] > 0)) return fail(c, SDC_EINVAL, "bad W or Le");
+    d.W[k] = m->W[k];
+    d.invW[k] = 1.0 / m->W[k];
+    d.Rk[k] = RU / m->W[k];
+    d.invLe[k] = 1.0 / m->Le[k];
+    const double *a = m->nasa + 7 * k;
+    for (int i = 0; i < 5; ++i) {
+      d.cp[k][i] = a[i];
+      d.hc[k][i] = a[i] / (i + 1);
+    }
+    d.h6[k] = a[5];
+    for (int i = 0; i < 4; ++i) d.sc[k][i] = a[i + 1] / (i + 1);
+    d.s7[k] = a[6];
+  }
+  for (int j = 0; j < m->nr; ++j) {
+    if (!(m->A[j] > 0)) return fail(c, SDC_EINVAL, "pre-exponential must be > 0");
+    d.lnA[j] = std::log(m->A[j]);
+    d.beta[j] = m->b[j];
+    d.EaR[j] = m->Ea[j] / RU;
+    int nr_ = 0, np_ = 0, dnu = 0;
+    d.rs[j][0] = d.rs[j][1] = d.ps[j][0] = d.ps[j][1] = -1;
+    for (int k = 0; k < m->ns; ++k) {
+      const int f = m->nu_f[j * m->ns + k], r = m->nu_r[j * m->ns + k];
+      if (f < 0 || r < 0) return fail(c, SDC_EINVAL, "negative stoichiometric coefficient");
+      for (int i = 0; i < f; ++i) {
+        if (nr_ == 2) return fail(c, SDC_EINVAL, "more than two reactant molecules");
+        d.rs[j][nr_++] = k;
+      }
+      for (int i = 0; i < r; ++i) {
+        if (np_ == 2) return fail(c, SDC_EINVAL, "more than two product molecules");
+        d.ps[j][np_++] = k;
+      }
+      dnu += r - f;
+    }
+    if (nr_ == 0 || np_ == 0) return fail(c, SDC_EINVAL, "reaction without reactants or products");
+    d.dnu[j] = dnu;
+  }
+  // eighth-order narrow-stencil matrix M(m47, m48), Section 2.2: rows 1..4
+  // as printed, rows 5..8 the negated reversals of rows 4..1.
+  const double a47 = m->m47, a48 = m->m48;
+  const double top[4][8] = {
+      {5.0 / 336 + a48, -83.0 / 3600 - a47 / 5 - 14 * a48 / 5, 299.0 / 50400 + 2 * a47 / 5 + 13 * a48 / 5,
+       17.0 / 12600 - a47 / 5 - 4 * a48 / 5, 1.0 / 1120, 0, 0, 0},
+      {-11.0 / 560 - 2 * a48, -31.0 / 360 + a47 + 3 * a48, 41.0 / 200 - 9 * a47 / 5 + 4 * a48 / 5,
+       -5927.0 / 50400 + 4 * a47 / 5 - 9 * a48 / 5, 17.0 / 600 - a47 / 5 - 4 * a48 / 5,
+       -503.0 / 50400 + a47 / 5 + 4 * a48 / 5, 0, 0},
+      {-1.0 / 280, 1097.0 / 5040 - 2 * a47 + 6 * a48, -1349.0 / 10080 + 3 * a47 - 12 * a48,
+       -887.0 / 5040 - a47 + 6 * a48, 3613.0 / 50400 + 4 * a47 / 5 - 9 * a48 / 5,
+       467.0 / 25200 - 3 * a47 / 5 + 18 * a48 / 5, 139.0 / 25200 - a47 / 5 - 9 * a48 / 5, 0},
+      {17.0 / 1680 + 2 * a48, -319.0 / 2520 + 2 * a47 - 8 * a48, -919.0 / 5040 - 2 * a47 + 6 * a48,
+       -445.0 / 2016, 583.0 / 720 - a47 + 6 * a48, -65.0 / 224 - 7 * a48, a47, a48},
+  };
+  for (int r = 0; r < 4; ++r)
+    for (int col = 0; col < 8; ++col) {
+      d.M[r][col] = top[r][col];
+      d.M[7 - r][7 - col] = -top[r][col];
+    }
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, hipMemcpy(c->d_mech, &d, sizeof d, hipMemcpyHostToDevice));
+  c->ops = o;
+  c->has_mech = true;
+  return SDC_OK;
+}
+
+int prim_to_cons(sdc_context *c, const box_desc *box, const double *p, const double *T,
+                 const double *Y, const double *u, double *U, void *stream) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!p || !T || !Y || !u || !U) return fail(c, SDC_EINVAL, "null field pointer");
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan *pl;
+  rc = get_plan(c, 1, box, nullptr, &pl);
+  if (rc) return rc;
+  const LaunchCtx l = make_lc(c, pl, (hipStream_t)stream);
+  c->ops->prim_to_cons(l, p, T, Y, u, FRef{U, nullptr});
+  c->ops->ghost(l, FRef{U, nullptr});
+  HIPCHECK(c, hipGetLastError());
+  return SDC_OK;
+}
+
+int rhs_eval(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsigned parts,
+             void *stream) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!U || !dUdt) return fail(c, SDC_EINVAL, "null field pointer");
+  if (parts == 0 || (parts & ~7u)) return fail(c, SDC_EINVAL, "bad parts mask");
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan *pl;
+  rc = get_plan(c, 1, box, nullptr, &pl);
+  if (rc) return rc;
+  const int ns = c->ops->ns;
+  const size_t need = ((size_t)pl->totS * (8 + 3 * ns + 9) + 64) * sizeof(double);
+  if (need > c->scratch_bytes) {
+    HIPCHECK(c, hipStreamSynchronize((hipStream_t)stream));
+    if (c->scratch) (void)hipFree(c->scratch);
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    HIPCHECK(c, hipMalloc(&c->scratch, need));
+    c->scratch_bytes = need;
+  }
+  double *P = c->scratch;
+  double *G = P + ((((size_t)pl->totS * (8 + 3 * ns)) + 31) & ~size_t(31));
+  const LaunchCtx l = make_lc(c, pl, (hipStream_t)stream);
+  eval_rhs_g(c->ops, l, FRef{U, nullptr}, P, G, FRef{dUdt, nullptr}, parts);
+  HIPCHECK(c, hipGetLastError());
+  return SDC_OK;
+}
+
+int sdc_workspace_size(const sdc_context *c, int nbox, const box_desc *boxes,
+                       const sdc_scheme *scheme, size_t *bytes) {
+  if (!c || !bytes || nbox < 1 || !boxes) return SDC_EINVAL;
+  if (!c->has_mech) return SDC_ENOMECH;
+  sdc_context *cc = const_cast<sdc_context *>(c);
+  for (int i = 0; i < nbox; ++i)
+    if (check_box(cc, boxes + i)) return SDC_EINVAL;
+  if (check_scheme(cc, scheme)) return SDC_EINVAL;
+  Plan p;
+  for (int i = 0; i < nbox; ++i) {
+    p.totS += (long long)(boxes[i].nx + 8) * (boxes[i].ny + 8) * (boxes[i].nz + 8);
+    p.totI += (long long)boxes[i].nx * boxes[i].ny * boxes[i].nz;
+  }
+  *bytes = ws_layout(&p, c->ops->ns, scheme).total * sizeof(double);
+  return SDC_OK;
+}
+
+int sdc_step(sdc_context *c, const box_desc *box, double *U, double dt, int nsteps,
+             const sdc_scheme *scheme, void *workspace, size_t ws_bytes, void *stream) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  rc = check_scheme(c, scheme);
+  if (rc) return rc;
+  if (!U) return fail(c, SDC_EINVAL, "null state");
+  if (!(dt > 0) || nsteps < 1) return fail(c, SDC_EINVAL, "dt must be > 0 and nsteps >= 1");
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan *pl;
+  rc = get_plan(c, 1, box, nullptr, &pl);
+  if (rc) return rc;
+  rc = run_sdc(c, pl, FRef{U, nullptr}, dt, nsteps, scheme, workspace, ws_bytes, (hipStream_t)stream);
+  if (rc) return rc;
+  HIPCHECK(c, hipGetLastError());
+  return SDC_OK;
+}
+
+int sdc_step_batched(sdc_context *c, int nbox, const box_desc *boxes, double *const *U, double dt,
+                     int nsteps, const sdc_scheme *scheme, void *workspace, size_t ws_bytes,
+                     void *stream) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  if (nbox < 1 || !boxes || !U) return fail(c, SDC_EINVAL, "bad batch");
+  for (int i = 0; i < nbox; ++i) {
+    int rc = check_box(c, boxes + i);
+    if (rc) return rc;
+    if (!U[i]) return fail(c, SDC_EINVAL, "null state");
+  }
+  int rc = check_scheme(c, scheme);
+  if (rc) return rc;
+  if (!(dt > 0) || nsteps < 1) return fail(c, SDC_EINVAL, "dt must be > 0 and nsteps >= 1");
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan *pl;
+  rc = get_plan(c, nbox, boxes, U, &pl);
+  if (rc) return rc;
+  rc = run_sdc(c, pl, FRef{nullptr, pl->d_Utab}, dt, nsteps, scheme, workspace, ws_bytes,
+               (hipStream_t)stream);
+  if (rc) return rc;
+  HIPCHECK(c, hipGetLastError());
+  return SDC_OK;
+}
+
+int last_status(sdc_context *c, void *stream) {
+  if (!c) return SDC_EINVAL;
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, hipStreamSynchronize((hipStream_t)stream));
+  int e = 0;
+  HIPCHECK(c, hipMemcpy(&e, c->d_err, sizeof e, hipMemcpyDeviceToHost));
+  if (e) {
+    HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
+    return fail(c, SDC_ETEMP, "device error flags " + std::to_string(e) +
+                                  " (1 Newton not converged, 2 T out of range, 4 rho <= 0)");
+  }
+  return SDC_OK;
+}
+
+const char *last_error_message(const sdc_context *c) { return c ? c->msg.c_str() : "null context"; }
+
+// Tuning hooks (not part of the documented interface): force the tile
+// shapes of the interior and stored index spaces (0 = automatic) and cap the
+// grid size of every launch (0 = one workgroup per item).
+int sdc_set_tiles(sdc_context *c, int ix, int iy, int iz, int sx, int sy, int sz, int grid_cap) {
+  if (!c) return SDC_EINVAL;
+  if (ix * iy * iz > 256 || sx * sy * sz > 256 || ix < 0 || sx < 0)
+    return fail(c, SDC_EINVAL, "tile larger than 256 threads");
+  c->forceI = TileShape{ix, iy, iz};
+  c->forceS = TileShape{sx, sy, sz};
+  c->grid_cap = grid_cap;
+  return SDC_OK;
+}
+
+int sdc_profile_enable(sdc_context *c, int enable) {
+  if (!c) return SDC_EINVAL;
+  if (enable) {
+    if (!c->prof) c->prof = std::make_unique<Profiler>();
+    c->prof->recs.clear();
+    c->prof->used = 0;
+  } else {
+    c->prof.reset();
+  }
+  return SDC_OK;
+}
+
+int sdc_profile_read(sdc_context *c, void *stream, double *total_ms, int *count) {
+  if (!c || !total_ms || !count) return SDC_EINVAL;
+  for (int k = 0; k < K_NKERNELS; ++k) {
+    total_ms[k] = 0.0;
+    count[k] = 0;
+  }
+  if (!c->prof) return K_NKERNELS;
+  HIPCHECK(c, hipStreamSynchronize((hipStream_t)stream));
+  for (const auto &r : c->prof->recs) {
+    if (!r.b) continue;
+    float ms = 0.0f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, r.a, r.b));
+    total_ms[r.id] += ms;
+    count[r.id] += 1;
+  }
+  c->prof->recs.clear();
+  c->prof->used = 0;
+  return K_NKERNELS;
+}
+
+const char *sdc_kernel_name(int id) { return (id >= 0 && id < K_NKERNELS) ? KERNEL_NAMES[id] : ""; }
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Host-side interface to the kernels: one table of launch functions per
+// supported species count.
+#pragma once
+#include "nsdc_internal.h"
+
+namespace nsdc {
+
+
+// Kernel identities for the per-kernel timers.
+enum KernelId {
+  K_PRIM_TO_CONS = 0, K_GHOST, K_PRIMS, K_VGRAD, K_DIR_X, K_DIR_Y, K_DIR_Z, K_CHEM, K_SDC_NODE,
+  K_MR_FINE, K_NKERNELS
+};
+struct Profiler;
+// Record a HIP event on `s` before (begin) / after (end) a launch of kernel `id`
+// when a profiler is attached (no-ops otherwise).
+void prof_begin(Profiler *p, int id, hipStream_t s);
+void prof_end(Profiler *p, int id, hipStream_t s);
+
+// Everything a launch needs besides its field pointers: the box table, the
+// work-item lists of the three index spaces (interior tiles, stored tiles,
+// ghost-cell chunks), their tile shapes and the grid-size cap.
+struct LaunchCtx {
+  hipStream_t stream;
+  const BoxDev *boxes;
+  const Item *itemsI, *itemsS, *itemsG;
+  int nI, nS, nG;
+  TileShape tsI, tsS;
+  int cap;
+  const DevMech *mech;
+  int *err;
+  Profiler *prof;
+};
+
+struct Ops {
+  int ns;
+  void (*prim_to_cons)(const LaunchCtx &, const double *, const double *, const double *,
+                       const double *, FRef);
+  void (*ghost)(const LaunchCtx &, FRef);
+  void (*prims)(const LaunchCtx &, FRef, double *, FRef, int);
+  void (*vgrad)(const LaunchCtx &, const double *, double *);
+  void (*dir)(const LaunchCtx &, int, FRef, const double *, const double *, FRef, unsigned);
+  void (*chem)(const LaunchCtx &, FRef, double *);
+  void (*sdc_node)(const LaunchCtx &, FRef, FRef, const NodeArgs &);
+  void (*mr_fine)(const LaunchCtx &, FRef, FRef, const FineCoef *, const FinePtrs &);
+};
+
+// nullptr for an unsupported species count
+const Ops *ops_for(int ns);
+
+}  // namespace nsdc

@@ -1,0 +1,94 @@
+// Internal layouts shared by the host driver and the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define NSDC_NG 4
+#define NSDC_NSMAX 24
+#define NSDC_NRMAX 256
+#define NSDC_MAXNODES 40
+#define NSDC_MAXFINE 33
+
+// device error word bits
+#define NSDC_ERR_NEWTON 1
+#define NSDC_ERR_TRANGE 2
+#define NSDC_ERR_RHO 4
+
+// Mechanism tables in device memory.  Thermodynamic polynomials are stored
+// pre-scaled for Horner evaluation of c_p/R, h/(RT) and s/R; reactions as
+// (at most) two reactant and two product species indices (-1 = none).
+struct DevMech {
+  int ns, nr;
+  double Tlo, Thi;
+  double mu_ref, inv_Tref, mu_exp, inv_Pr, bulk;
+  double W[NSDC_NSMAX], invW[NSDC_NSMAX], Rk[NSDC_NSMAX], invLe[NSDC_NSMAX];
+  double cp[NSDC_NSMAX][5];   // a1..a5
+  double hc[NSDC_NSMAX][5];   // a1, a2/2, a3/3, a4/4, a5/5
+  double h6[NSDC_NSMAX];      // a6
+  double sc[NSDC_NSMAX][4];   // a2, a3/2, a4/3, a5/4
+  double s7[NSDC_NSMAX];      // a7
+  double lnA[NSDC_NRMAX], beta[NSDC_NRMAX], EaR[NSDC_NRMAX];
+  int rs[NSDC_NRMAX][2], ps[NSDC_NRMAX][2];
+  int dnu[NSDC_NRMAX];
+  double M[8][8];             // narrow-stencil matrix, [m+3][n+3]
+};
+
+// One box of a batch.  offS / offI: offsets (in cells) of this box inside
+// arena arrays laid out box after box with (stored | interior) cells per
+// component.
+struct BoxDev {
+  int nx, ny, nz;
+  int sx, sy, sz;
+  long long offS, offI;
+  double idx[3], idx2[3];
+};
+
+// One work item: a tile origin of one box (interior or stored coordinates
+// depending on the stage) or, for the ghost fill, a chunk of ghost cells.
+struct Item {
+  int box, x0, y0, z0;
+};
+
+// A field set: per-box pointer table (user arrays) or an arena base.
+struct FRef {
+  double *base;
+  double *const *tab;
+  __host__ __device__ double *get(int box, long long off) const {
+    return tab ? tab[box] : base + off;
+  }
+};
+
+struct TileShape {
+  int tx, ty, tz;
+};
+
+// Single-rate SDC node update arguments (passed by value).
+struct NodeArgs {
+  const double *Fold[8];   // F^k at the nodes 0..M
+  double S[8];             // row m of the node-to-node matrix S
+  int nnodes;
+  const double *Fnew_m, *Fold_m;
+  double dtau, dt;
+};
+
+// Coefficients of one coarse interval of the multirate sweep, in units of
+// the step: rows of S_{2,1} and S_{2,2} restricted to the interval's fine
+// nodes, and the fine sub-step lengths (device memory, one per interval).
+struct FineCoef {
+  double S21[NSDC_MAXFINE][8];
+  double S22[NSDC_MAXFINE][NSDC_MAXFINE];
+  double dtq[NSDC_MAXFINE];
+  int n1;          // coarse nodes M1 + 1
+  int nq;          // fine sub-steps in the interval
+};
+
+// Node arrays of one coarse interval (passed by value; arena bases).
+struct FinePtrs {
+  const double *F1old[8];              // f1 at the coarse nodes, iteration k
+  const double *F1new_p, *F1old_p;     // f1 at the interval's left coarse node, k+1 and k
+  const double *F2old[NSDC_MAXFINE];   // f2 at the interval's fine nodes, iteration k
+  double *F2new[NSDC_MAXFINE];         // f2 at the interval's fine nodes, iteration k+1
+  int q0_known;    // f2 at the first fine node is the step-start value F2old[0]
+  int eval_last;   // evaluate and store f2 at the interval's last fine node
+  double dt;
+};

@@ -26,15 +26,15 @@ SIZES = (16, 24, 32, 40, 48)
 
 WORKLOADS = {
     "box16_sdc": dict(shape=(16, 16, 16), dx=1e-4, mech="mech9", recipe="sines", seed=1,
-                      scheme=dict(kind="sdc", n_coarse=4, sweeps=6), steps=1),
+                      scheme=dict(kind="sdc", n_coarse=4, sweeps=6, n_fine=0), steps=1),
     "box128_mrsdc": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9", recipe="turb", seed=2, kmax=16,
-                         scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, repeat=1, sweeps=6), steps=10),
+                         scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=10),
     "box256_mrsdc": dict(shape=(256, 256, 256), dx=1e-4, mech="mech21", recipe="turb", seed=3, kmax=32,
-                         scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, repeat=1, sweeps=6), steps=5),
+                         scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=5),
     "batch240_sdc": dict(nbox=240, dx=1e-4, mech="mech9", recipe="sines", seed=1000,
-                         scheme=dict(kind="sdc", n_coarse=4, sweeps=6), steps=1),
+                         scheme=dict(kind="sdc", n_coarse=4, sweeps=6, n_fine=0), steps=1),
     "box64_adjoint": dict(shape=(64, 64, 64), dx=1e-4, mech="mech9", recipe="sines", seed=5,
-                          scheme=dict(kind="sdc", n_coarse=4, sweeps=6), steps=5),
+                          scheme=dict(kind="sdc", n_coarse=4, sweeps=6, n_fine=0), steps=5),
 }
 
 

@@ -1,0 +1,179 @@
+"""Parity of the HIP path with the oracle (right-hand side, SDC, MRSDC).
+Every test calls the library through its C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sdc as osdc
+from synth import fields, mechanism
+from synth.workloads import WORKLOADS, make_primitives, time_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1309_7327_amd import narrowsdc as N  # noqa: E402
+import gpu_util as G  # noqa: E402
+
+MECHS = {}
+
+
+def mech(kind):
+    if kind not in MECHS:
+        m = mechanism.load(kind)
+        ctx = N.Context(0)
+        ctx.set_mechanism(m)
+        MECHS[kind] = (m, oracle.Mechanism(m), ctx)
+    return MECHS[kind]
+
+
+@pytest.mark.parametrize("kind,shape", [("mech9", (16, 16, 16)), ("mech9le", (5, 6, 7)),
+                                        ("mech21", (9, 12, 20)), ("mech9", (24, 20, 36))])
+def test_prim_to_cons(kind, shape):
+    m, om, ctx = mech(kind)
+    prim = fields.sines(shape, 1e-4, m["ns"], 7)
+    bx, U = G.device_state(ctx, prim, 1e-4)
+    Ug = G.host(U)
+    Uo = oracle.prim_to_cons(om, prim)
+    ok, rep = G.compare(G.interior(Ug), Uo, tol=1e-14)
+    assert ok, G.fmt(rep)
+    # ghost layers are the periodic images
+    np.testing.assert_array_equal(Ug[:, :4], Ug[:, -8:-4])
+    np.testing.assert_array_equal(Ug[:, :, :, -4:], Ug[:, :, :, 4:8])
+
+
+@pytest.mark.parametrize("parts", [N.RHS_HYP, N.RHS_DIFF, N.RHS_REACT, N.RHS_ALL])
+@pytest.mark.parametrize("kind,shape,dx", [
+    ("mech9", (16, 16, 16), 1e-4),            # the 16^3 workload box
+    ("mech9le", (5, 6, 7), (1e-4, 1.2e-4, 0.9e-4)),   # ragged, anisotropic, V_c and bulk active
+    ("mech21", (9, 12, 20), 1e-4),
+    ("mech9", (24, 20, 36), 1e-4),            # several tiles with ragged tails
+])
+def test_rhs_eval_parity(kind, shape, dx, parts):
+    m, om, ctx = mech(kind)
+    prim = fields.sines(shape, dx, m["ns"], 11)
+    bx, U = G.device_state(ctx, prim, dx)
+    F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
+    ctx.rhs_eval(bx, U, F, parts)
+    ctx.check_status()
+    Uo = oracle.prim_to_cons(om, prim)
+    fref, floor = G.ulp_floor(lambda V: oracle.rhs(om, V, dx, parts=parts), Uo)
+    ok, rep = G.compare(G.host(F), fref, floor)
+    print(kind, shape, parts, G.fmt(rep))
+    assert ok, G.fmt(rep)
+
+
+def test_rhs_eval_deterministic_and_tile_independent():
+    m, om, ctx = mech("mech9")
+    shape = (20, 18, 40)
+    prim = fields.sines(shape, 1e-4, m["ns"], 5)
+    bx, U = G.device_state(ctx, prim, 1e-4)
+    outs = []
+    for tiles in [((0, 0, 0), (0, 0, 0)), ((16, 4, 4), (16, 4, 4)), ((64, 2, 2), (8, 8, 4)),
+                  ((8, 8, 2), (32, 8, 1))]:
+        ctx.set_tiles(*tiles, grid_cap=37)
+        for _ in range(2):
+            F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
+            ctx.rhs_eval(bx, U, F, N.RHS_ALL)
+            outs.append(G.host(F))
+    ctx.set_tiles()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+def _sdc_oracle(om, U0, dx, dt, sch, nsteps, perturb=None):
+    if sch["n_fine"] == 0:
+        f = lambda U, t: oracle.rhs(om, U, dx, nthreads=0)
+        return osdc.sdc_run(f, U0, 0.0, dt, osdc.gauss_lobatto(sch["n_coarse"]), sch["sweeps"], nsteps,
+                            perturb)
+    f1 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.AD)
+    f2 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.REACT)
+    t1, t2, pieces = osdc.mr_nodes(sch["n_coarse"], sch["n_fine"], sch["fine_repeat"])
+    return osdc.mrsdc_run(f1, f2, U0, 0.0, dt, t1, t2, pieces, sch["sweeps"], nsteps, perturb)
+
+
+def _run_gpu_sdc(ctx, bx, U, dt, sch, nsteps):
+    s = N.scheme(sch["n_coarse"], sch["sweeps"], sch["n_fine"], sch.get("fine_repeat", 1))
+    ws, nb = N.workspace(ctx, [bx], s)
+    ctx.sdc_step(bx, U, dt, nsteps, s, ws, nb)
+    ctx.check_status()
+
+
+@pytest.mark.parametrize("kind,shape,sch,nsteps", [
+    ("mech9", (16, 16, 16), dict(n_coarse=4, sweeps=6, n_fine=0), 1),            # the 16^3 workload
+    ("mech9le", (6, 5, 7), dict(n_coarse=3, sweeps=4, n_fine=0), 3),
+    ("mech9", (8, 8, 8), dict(n_coarse=4, sweeps=6, n_fine=5, fine_repeat=1), 2),  # MRSDC type (b)
+    ("mech21", (6, 8, 5), dict(n_coarse=3, sweeps=4, n_fine=3, fine_repeat=2), 1),  # MRSDC type (c)
+])
+def test_sdc_step_parity(kind, shape, sch, nsteps):
+    m, om, ctx = mech(kind)
+    prim = fields.sines(shape, 1e-4, m["ns"], 13)
+    bx, U = G.device_state(ctx, prim, 1e-4)
+    U0g = G.interior(G.host(U)).copy()
+    dt = time_step("box16_sdc")
+    _run_gpu_sdc(ctx, bx, U, dt, sch, nsteps)
+    Ug = G.interior(G.host(U))
+    U0 = oracle.prim_to_cons(om, prim)
+    ref, floor, dfloor = G.ulp_floor_step(lambda V, pt: _sdc_oracle(om, V, 1e-4, dt, sch, nsteps, pt), U0)
+    ok, rep = G.compare(Ug, ref, floor)
+    okd, repd = G.compare(Ug - U0g, ref - U0, dfloor, state=ref)
+    print("U ", G.fmt(rep))
+    print("dU", G.fmt(repd))
+    assert ok and okd, G.fmt(repd)
+
+
+@pytest.mark.parametrize("name", ["box128_mrsdc", "box256_mrsdc"])
+def test_full_size_step_on_periodic_tiling(name):
+    """The full-size multirate step in the benchmark's launch configuration,
+    on a state that repeats a 16^3 box periodically: the exact result is the
+    16^3 box's step repeated, which the oracle computes."""
+    wl = WORKLOADS[name]
+    m, om, ctx = mech(wl["mech"])
+    n = wl["shape"][0]
+    small = make_primitives(name, m, shape_override=(16, 16, 16))
+    reps = (n // 16,) * 3
+    big = fields.tile(small, reps)
+    bx, U = G.device_state(ctx, big, wl["dx"])
+    dt = time_step(name)
+    sch = dict(wl["scheme"])
+    U0g = G.interior(G.host(U))[:, :16, :16, :16].copy()
+    _run_gpu_sdc(ctx, bx, U, dt, sch, 1)
+    Ug = G.interior(G.host(U))
+    del U
+    torch.cuda.empty_cache()
+    U0s = oracle.prim_to_cons(om, small)
+    ref, floor, dfloor = G.ulp_floor_step(lambda V, pt: _sdc_oracle(om, V, wl["dx"], dt, sch, 1, pt), U0s)
+    reps_q = (1,) + reps
+    ok, rep = G.compare(Ug, np.tile(ref, reps_q), floor)
+    okd, repd = G.compare(Ug - np.tile(U0g, reps_q), np.tile(ref - U0s, reps_q), dfloor, state=ref)
+    print("U ", G.fmt(rep))
+    print("dU", G.fmt(repd))
+    assert ok and okd, G.fmt(repd)
+
+
+def test_sampled_cells_of_full_size_rhs():
+    """Full 128^3 turbulent flame state: right-hand side at sampled cells."""
+    name = "box128_mrsdc"
+    wl = WORKLOADS[name]
+    m, om, ctx = mech(wl["mech"])
+    prim = make_primitives(name, m)
+    bx, U = G.device_state(ctx, prim, wl["dx"])
+    shape = wl["shape"]
+    F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
+    ctx.rhs_eval(bx, U, F, N.RHS_ALL)
+    ctx.check_status()
+    Fh = G.host(F)
+    Ui = oracle.prim_to_cons(om, prim)
+    rng = np.random.default_rng(3)
+    cells = rng.integers(0, shape[0], size=(96, 3))
+    cells[:8] = [[0, 0, 0], [127, 127, 127], [0, 127, 3], [64, 0, 127], [1, 2, 3], [126, 1, 0], [3, 3, 126], [127, 0, 0]]
+    ref = oracle.rhs_cells(om, Ui, wl["dx"], cells)
+    rng2 = np.random.default_rng(12345)
+    ref_p = oracle.rhs_cells(om, Ui * (1 + 2.0 ** -52 * rng2.standard_normal(Ui.shape)), wl["dx"], cells)
+    got = np.stack([Fh[:, z, y, x] for x, y, z in cells])
+    floor = np.abs(ref_p - ref).max(axis=0)
+    ok, rep = G.compare(got.T, ref.T, floor)
+    print(G.fmt(rep))
+    assert ok, G.fmt(rep)
