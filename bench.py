@@ -45,11 +45,17 @@ def work_model(ns, n_coarse, n_fine_per_interval):
     chem_flops = 32 * ns + 75 * (21 if ns == 9 else 84)
     newton = 5 * ns * 20
     r = n_fine_per_interval
-    fine_flops = r * (chem_flops + newton + nu * (2 * n_coarse + 6) + ns * (2 * r + 4))
-    fine_bytes = 8 * (2 * nu + (n_coarse + 2) * nu + (r + 1) * ns + r * ns)
+    n1 = n_coarse
+    # fine sub-sweep of one coarse interval: r chemistry sub-steps per cell
+    # (Newton, rates, update with the precomputed increments) ...
+    step_flops = r * (chem_flops + newton + 2 * nu)
+    step_bytes = 8 * (2 * nu + r * nu + r * ns)
+    # ... and the quadrature increments S21 F1 + S22 F2 of those sub-steps
+    src_flops = r * (nu * (2 * n1 + 3) + ns * 2 * 6)
+    src_bytes = 8 * (nu * (n1 + 1) + ns * (r + 1) + r * nu)
     return {
         "dir_x": (dir_flops, dir_bytes), "dir_y": (dir_flops, dir_bytes), "dir_z": (dir_flops, dir_bytes),
-        "mr_fine": (fine_flops, fine_bytes),
+        "mr_fine": (step_flops, step_bytes), "mr_src": (src_flops, src_bytes),
         "prims": (newton + 40 * ns, 8 * (nu + np_)),
     }
 
@@ -114,6 +120,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="box128_mrsdc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -143,6 +151,12 @@ def main():
         r = (sch_d["n_fine"] - 1) * sch_d["fine_repeat"]
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx = N.Context(0)
     ctx.set_mechanism(mech)
     prim = make_primitives(args.workload, mech)

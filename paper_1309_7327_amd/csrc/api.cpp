@@ -187,7 +187,8 @@ void prof_end(Profiler *p, int id, hipStream_t s) {
 }  // namespace nsdc
 
 static const char *KERNEL_NAMES[K_NKERNELS] = {"prim_to_cons", "ghost", "prims", "vgrad", "dir_x",
-                                               "dir_y", "dir_z", "chem", "sdc_node", "mr_fine"};
+                                               "dir_y", "dir_z", "chem", "sdc_node", "mr_fine",
+                                               "mr_src"};
 
 struct sdc_context {
   int device = 0;
@@ -207,6 +208,7 @@ struct sdc_context {
   TileShape forceI{0, 0, 0}, forceS{0, 0, 0};
   int grid_cap = 0;
   std::unique_ptr<Profiler> prof;
+  bool smc_stencil = false;
 };
 
 namespace {
@@ -228,7 +230,7 @@ int check_box(sdc_context *c, const box_desc *b) {
   if (b->ng != NSDC_NG) return fail(c, SDC_EINVAL, "ghost layers must be 4");
   if (!(b->dx > 0) || !(b->dy > 0) || !(b->dz > 0)) return fail(c, SDC_EINVAL, "grid spacing must be > 0");
   const long long s = (long long)(b->nx + 8) * (b->ny + 8) * (b->nz + 8);
-  if (s > (1LL << 31)) return fail(c, SDC_EINVAL, "box too large");
+  if (s >= (1LL << 28)) return fail(c, SDC_EINVAL, "box too large (stored cells must be < 2^28)");
   return SDC_OK;
 }
 
@@ -322,6 +324,7 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.mech = c->d_mech;
   l.err = c->d_err;
   l.prof = c->prof.get();
+  l.smc_stencil = c->smc_stencil;
   return l;
 }
 
@@ -350,8 +353,8 @@ int check_scheme(sdc_context *c, const sdc_scheme *s) {
 
 // workspace layout (doubles), in order: P, G, U buffers, F arrays
 struct WsLayout {
-  size_t P, G, Ub, F1, F2, total;
-  int nUb, nF1, nF2;
+  size_t P, G, Ub, F1, F2, A, total;
+  int nUb, nF1, nF2, nA;
 };
 
 WsLayout ws_layout(const Plan *p, int ns, const sdc_scheme *s) {
@@ -363,6 +366,7 @@ WsLayout ws_layout(const Plan *p, int ns, const sdc_scheme *s) {
   w.nUb = mr ? 1 : 2;
   w.nF1 = 1 + 2 * M1;
   w.nF2 = mr ? 1 + 2 * M2 : 0;
+  w.nA = mr ? (s->n_fine - 1) * s->fine_repeat : 0;   // fine sub-steps of one coarse interval
   size_t off = 0;
   auto take = [&](size_t n) { size_t o = off; off += (n + 31) & ~size_t(31); return o; };
   w.P = take((size_t)p->totS * nP);
@@ -370,6 +374,7 @@ WsLayout ws_layout(const Plan *p, int ns, const sdc_scheme *s) {
   w.Ub = take((size_t)p->totS * nU * w.nUb);
   w.F1 = take((size_t)p->totI * nU * w.nF1);
   w.F2 = take((size_t)p->totI * ns * w.nF2);
+  w.A = take((size_t)p->totI * nU * w.nA);
   w.total = off;
   return w;
 }
@@ -388,6 +393,7 @@ int fine_tables(sdc_context *c, const sdc_scheme *s) {
     std::memset(&f, 0, sizeof f);
     f.n1 = M1 + 1;
     f.nq = r;
+    f.nfine = s->n_fine;
     // fine nodes of this coarse interval: `repeat` copies of the fine rule
     std::vector<long double> tf(r + 1);
     const long double a = t1[p], b = t1[p + 1];
@@ -404,8 +410,8 @@ int fine_tables(sdc_context *c, const sdc_scheme *s) {
       const int piece = q / (s->n_fine - 1);
       std::vector<long double> loc(tf.begin() + piece * (s->n_fine - 1),
                                    tf.begin() + piece * (s->n_fine - 1) + s->n_fine);
-      for (int j = 0; j < s->n_fine; ++j)
-        f.S22[q][piece * (s->n_fine - 1) + j] = (double)lagrange_integral(loc, j, tf[q], tf[q + 1]);
+      f.jlo[q] = piece * (s->n_fine - 1);
+      for (int j = 0; j < s->n_fine; ++j) f.S22[q][j] = (double)lagrange_integral(loc, j, tf[q], tf[q + 1]);
     }
   }
   if (c->d_fine) (void)hipFree(c->d_fine);
@@ -492,65 +498,74 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
   const int r = (s->n_fine - 1) * s->fine_repeat;
   const int M2 = M * r;
   const long long f2I = p->totI * ns;
-  double *F10 = W + L.F1, *F20 = W + L.F2;
-  std::vector<double *> F1A(M + 1), F1B(M + 1), F2A(M2 + 1), F2B(M2 + 1);
+  // node values live in slots of two arenas: slot 0 holds the step-start
+  // value, slots 1..M (1..M2) one sweep's values, M+1..2M (M2+1..2M2) the
+  // other's; roles rotate between sweeps and steps by renaming slots.
+  double *F1base = W + L.F1, *F2base = W + L.F2;
+  auto F1p = [&](int slot) { return F1base + fI * slot; };
+  auto F2p = [&](int slot) { return F2base + f2I * slot; };
+  int s10 = 0, s20 = 0;
+  std::vector<int> s1A(M + 1), s1B(M + 1), s2A(M2 + 1), s2B(M2 + 1);
   for (int m = 1; m <= M; ++m) {
-    F1A[m] = W + L.F1 + fI * m;
-    F1B[m] = W + L.F1 + fI * (M + m);
+    s1A[m] = m;
+    s1B[m] = M + m;
   }
   for (int q = 1; q <= M2; ++q) {
-    F2A[q] = W + L.F2 + f2I * q;
-    F2B[q] = W + L.F2 + f2I * (M2 + q);
+    s2A[q] = q;
+    s2B[q] = M2 + q;
   }
   FRef Ucur{W + L.Ub, nullptr};
-  eval_rhs_g(o, l, Uuser, P, G, FRef{F10, nullptr}, RHS_AD);
-  o->chem(l, Uuser, F20);
-  std::vector<const double *> F1old(M + 1), F2old(M2 + 1);
-  std::vector<double *> F1new(M + 1), F2new(M2 + 1);
+  eval_rhs_g(o, l, Uuser, P, G, FRef{F1p(s10), nullptr}, RHS_AD);
+  o->chem(l, Uuser, F2p(s20));
+  std::vector<int> F1old(M + 1), F2old(M2 + 1), F1new(M + 1), F2new(M2 + 1);
   for (int step = 0; step < nsteps; ++step) {
-    for (int j = 0; j <= M; ++j) F1old[j] = F10;
-    for (int q = 0; q <= M2; ++q) F2old[q] = F20;
+    for (int j = 0; j <= M; ++j) F1old[j] = s10;
+    for (int q = 0; q <= M2; ++q) F2old[q] = s20;
     for (int k = 0; k < K; ++k) {
-      F1new[0] = F10;
-      F2new[0] = F20;
-      for (int m = 1; m <= M; ++m) F1new[m] = (k % 2 == 0) ? F1A[m] : F1B[m];
-      for (int q = 1; q <= M2; ++q) F2new[q] = (k % 2 == 0) ? F2A[q] : F2B[q];
+      F1new[0] = s10;
+      F2new[0] = s20;
+      for (int m = 1; m <= M; ++m) F1new[m] = (k % 2 == 0) ? s1A[m] : s1B[m];
+      for (int q = 1; q <= M2; ++q) F2new[q] = (k % 2 == 0) ? s2A[q] : s2B[q];
       const bool last = step == nsteps - 1 && k == K - 1;
       FRef Uout = Ucur;
       for (int pi = 0; pi < M; ++pi) {
         FRef Uin = pi == 0 ? Uuser : Ucur;
-        if (pi > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{F1new[pi], nullptr}, RHS_AD);
+        if (pi > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{F1p(F1new[pi]), nullptr}, RHS_AD);
         Uout = (k == K - 1 && pi == M - 1) ? Uuser : Ucur;
         FinePtrs fp{};
-        for (int j = 0; j <= M; ++j) fp.F1old[j] = F1old[j];
-        fp.F1new_p = F1new[pi];
-        fp.F1old_p = F1old[pi];
+        fp.F1base = F1base;
+        fp.F2base = F2base;
+        fp.f1slot = fI;
+        fp.f2slot = f2I;
+        for (int j = 0; j <= M; ++j) fp.F1old[j] = (unsigned short)F1old[j];
+        fp.F1new_p = (unsigned short)F1new[pi];
+        fp.F1old_p = (unsigned short)F1old[pi];
         for (int j = 0; j <= r; ++j) {
-          fp.F2old[j] = F2old[pi * r + j];
-          fp.F2new[j] = F2new[pi * r + j];
+          fp.F2old[j] = (unsigned short)F2old[pi * r + j];
+          fp.F2new[j] = (unsigned short)F2new[pi * r + j];
         }
         fp.q0_known = pi == 0;
         fp.eval_last = (pi == M - 1) && !last;
         fp.dt = dt;
-        o->mr_fine(l, Uin, Uout, c->d_fine + pi, fp);
+        o->mr_fine(l, Uin, Uout, c->d_fine + pi, fp, W + L.A, fI);
       }
-      if (!last) eval_rhs_g(o, l, Uout, P, G, FRef{F1new[M], nullptr}, RHS_AD);
-      for (int j = 0; j <= M; ++j) F1old[j] = F1new[j];
-      for (int q = 0; q <= M2; ++q) F2old[q] = F2new[q];
+      if (!last) eval_rhs_g(o, l, Uout, P, G, FRef{F1p(F1new[M]), nullptr}, RHS_AD);
+      F1old = F1new;
+      F2old = F2new;
     }
     if (step < nsteps - 1) {
-      double *fin1 = F1new[M], *fin2 = F2new[M2];
-      double *o1 = F10, *o2 = F20;
-      F10 = fin1;
-      F20 = fin2;
+      // recycle f(U_M) as the next step's f(U_0) by exchanging slot roles
+      const int fin1 = F1new[M], fin2 = F2new[M2];
       for (int m = 1; m <= M; ++m) {
-        if (F1A[m] == fin1) F1A[m] = o1;
-        if (F1B[m] == fin1) F1B[m] = o1;
+        if (s1A[m] == fin1) s1A[m] = s10;
+        if (s1B[m] == fin1) s1B[m] = s10;
       }
       for (int q = 1; q <= M2; ++q) {
-        if (F2A[q] == fin2) F2A[q] = o2;
-        if (F2B[q] == fin2) F2B[q] = o2;
+        if (s2A[q] == fin2) s2A[q] = s20;
+        if (s2B[q] == fin2) s2B[q] = s20;
       }
+      s10 = fin1;
+      s20 = fin2;
     }
   }
   o->ghost(l, Uuser);
@@ -647,6 +662,9 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
       dnu += r - f;
     }
     if (nr_ == 0 || np_ == 0) return fail(c, SDC_EINVAL, "reaction without reactants or products");
+    // absent second molecules point at the dummy species slot ns
+    for (int i = nr_; i < 2; ++i) d.rs[j][i] = m->ns;
+    for (int i = np_; i < 2; ++i) d.ps[j][i] = m->ns;
     d.dnu[j] = dnu;
   }
   // eighth-order narrow-stencil matrix M(m47, m48), Section 2.2: rows 1..4
@@ -669,10 +687,14 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
       d.M[r][col] = top[r][col];
       d.M[7 - r][7 - col] = -top[r][col];
     }
+  for (int o = 0; o < 9; ++o)
+    for (int col = 0; col < 9; ++col)
+      d.B[o][col] = ((o >= 1 && col >= 1) ? d.M[o - 1][col - 1] : 0.0) - ((o <= 7 && col <= 7) ? d.M[o][col] : 0.0);
   HIPCHECK(c, hipSetDevice(c->device));
   HIPCHECK(c, hipMemcpy(c->d_mech, &d, sizeof d, hipMemcpyHostToDevice));
   c->ops = o;
   c->has_mech = true;
+  c->smc_stencil = m->m47 == 3557.0 / 44100.0 && m->m48 == -2083.0 / 117600.0;
   return SDC_OK;
 }
 

@@ -61,11 +61,13 @@ __device__ __forceinline__ double s_R(const DevMech *__restrict__ m, int k, doub
 }
 
 // Temperature from the specific internal energy e by Newton's method on
-// e(T) = sum_k Y_k R_k T (h_k/(R_k T) - 1), dE/dT = c_v: start at 1000 K,
-// stop one iteration after the first update below 1e-12 T (at most 50).
+// e(T) = sum_k Y_k R_k T (h_k/(R_k T) - 1), de/dT = c_v: start at T0 (1000 K
+// unless a nearby temperature is known), stop one iteration after the first
+// update below 1e-12 T (at most 50).
 template <int NS>
-__device__ int temperature(const DevMech *__restrict__ m, const double *Y, double e, double &T) {
-  T = 1000.0;
+__device__ int temperature(const DevMech *__restrict__ m, const double *Y, double e, double &T,
+                           double T0 = 1000.0) {
+  T = T0;
   bool conv = false;
   for (int it = 0; it < 50; ++it) {
     const double invT = 1.0 / T;
@@ -87,10 +89,13 @@ __device__ int temperature(const DevMech *__restrict__ m, const double *Y, doubl
 // Chemistry source rho omega_k (mass action, reversible Arrhenius reactions,
 // reverse rate from the equilibrium constant of the Gibbs energies):
 //   k_r = k_f exp(sum nu g/RT) (R T / p_ref)^{sum nu}.
+// Every reaction has two reactant and two product slots; an absent molecule
+// points at slot NS, a dummy species with concentration 1 and g = 0, so the
+// loop body has no branches.
 template <int NS>
 __device__ void production(const DevMech *__restrict__ m, double rho, double T, const double *Y,
                            double *wdot) {
-  double c[NS], g[NS], w[NS];
+  double c[NS + 1], g[NS + 1], w[NS + 1];
   const double lnT = log(T), invT = 1.0 / T;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -98,25 +103,23 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
     g[k] = h_RT(m, k, T, invT) - s_R(m, k, T, lnT);
     w[k] = 0.0;
   }
+  c[NS] = 1.0;
+  g[NS] = 0.0;
+  w[NS] = 0.0;
   const double lnRTp = log(RU * T / PREF);
   const int nr = m->nr;
+#pragma unroll 2
   for (int j = 0; j < nr; ++j) {
     const int r0 = m->rs[j][0], r1 = m->rs[j][1], p0 = m->ps[j][0], p1 = m->ps[j][1];
     const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
-    double dg = g[p0] - g[r0];
-    if (p1 >= 0) dg += g[p1];
-    if (r1 >= 0) dg -= g[r1];
+    const double dg = (g[p0] + g[p1]) - (g[r0] + g[r1]);
     const double kf = exp(lnkf);
     const double kr = exp(lnkf + dg + m->dnu[j] * lnRTp);
-    double fwd = kf * c[r0];
-    if (r1 >= 0) fwd *= c[r1];
-    double rev = kr * c[p0];
-    if (p1 >= 0) rev *= c[p1];
-    const double q = fwd - rev;
+    const double q = kf * c[r0] * c[r1] - kr * c[p0] * c[p1];
     w[r0] -= q;
-    if (r1 >= 0) w[r1] -= q;
+    w[r1] -= q;
     w[p0] += q;
-    if (p1 >= 0) w[p1] += q;
+    w[p1] += q;
   }
 #pragma unroll
   for (int k = 0; k < NS; ++k) wdot[k] = w[k] * m->W[k];
@@ -126,7 +129,7 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
 // temperature.  Returns an error bit mask (0 = ok).
 template <int NS>
 __device__ int cell_state(const DevMech *__restrict__ m, const double *Uc, double &rho, double *u,
-                          double *Y, double &T) {
+                          double *Y, double &T, double T0 = 1000.0) {
   rho = Uc[0];
   const double ir = 1.0 / rho;
   u[0] = Uc[1] * ir;
@@ -136,7 +139,7 @@ __device__ int cell_state(const DevMech *__restrict__ m, const double *Uc, doubl
   for (int k = 0; k < NS; ++k) Y[k] = Uc[5 + k] * ir;
   const double e = Uc[4] * ir - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   int err = rho > 0.0 ? 0 : NSDC_ERR_RHO;
-  err |= temperature<NS>(m, Y, e, T);
+  err |= temperature<NS>(m, Y, e, T, T0);
   return err;
 }
 
@@ -343,41 +346,71 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
   }
 }
 
-// Row sums of the narrow-stencil matrix for one field at the two faces of
-// the centre cell: Rp[r] = sum_c M[r][c] u[1+c] (face i+1/2), Rm[r] with
-// u[c] (face i-1/2); the zero corners of M are skipped.
-struct Rows {
-  double p[8], m[8];
+// The narrow operator at the centre of nine samples, written through the 9x9
+// face-difference matrix B: (H_{i+1/2} - H_{i-1/2}) = sum_{o,c} a_o B_oc u_c with
+// B_oc = M_{o-1,c-1} - M_{o,c} (eqs. DaDu, H).  bvec computes v = B u once per
+// field (B is banded: row o spans columns o-4..o+4); every coefficient paired
+// with that field then costs a nine-term dot product.
+//
+// For the paper's default free parameters (m47 = 3557/44100, m48 =
+// -2083/117600) B is a compile-time table, so its entries are instruction
+// constants; other parameter values read B from the mechanism tables.
+struct Mat9 {
+  double v[9][9];
 };
-__device__ __forceinline__ void rows(const DevMech *__restrict__ mm, const double *u, Rows &R) {
-  const int lo[8] = {0, 0, 0, 0, 0, 1, 2, 3};
-  const int hi[8] = {4, 5, 6, 7, 7, 7, 7, 7};
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    double sp = 0.0, sm = 0.0;
-#pragma unroll
-    for (int c = lo[r]; c <= hi[r]; ++c) {
-      const double Mrc = mm->M[r][c];
-      sp += Mrc * u[1 + c];
-      sm += Mrc * u[c];
+constexpr Mat9 smc_face_matrix() {
+  const double a47 = 3557.0 / 44100.0, a48 = -2083.0 / 117600.0;
+  const double top[4][8] = {
+      {5.0 / 336 + a48, -83.0 / 3600 - a47 / 5 - 14 * a48 / 5, 299.0 / 50400 + 2 * a47 / 5 + 13 * a48 / 5,
+       17.0 / 12600 - a47 / 5 - 4 * a48 / 5, 1.0 / 1120, 0, 0, 0},
+      {-11.0 / 560 - 2 * a48, -31.0 / 360 + a47 + 3 * a48, 41.0 / 200 - 9 * a47 / 5 + 4 * a48 / 5,
+       -5927.0 / 50400 + 4 * a47 / 5 - 9 * a48 / 5, 17.0 / 600 - a47 / 5 - 4 * a48 / 5,
+       -503.0 / 50400 + a47 / 5 + 4 * a48 / 5, 0, 0},
+      {-1.0 / 280, 1097.0 / 5040 - 2 * a47 + 6 * a48, -1349.0 / 10080 + 3 * a47 - 12 * a48,
+       -887.0 / 5040 - a47 + 6 * a48, 3613.0 / 50400 + 4 * a47 / 5 - 9 * a48 / 5,
+       467.0 / 25200 - 3 * a47 / 5 + 18 * a48 / 5, 139.0 / 25200 - a47 / 5 - 9 * a48 / 5, 0},
+      {17.0 / 1680 + 2 * a48, -319.0 / 2520 + 2 * a47 - 8 * a48, -919.0 / 5040 - 2 * a47 + 6 * a48,
+       -445.0 / 2016, 583.0 / 720 - a47 + 6 * a48, -65.0 / 224 - 7 * a48, a47, a48},
+  };
+  double M[8][8] = {};
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 8; ++c) {
+      M[r][c] = top[r][c];
+      M[7 - r][7 - c] = -top[r][c];
     }
-    R.p[r] = sp;
-    R.m[r] = sm;
+  Mat9 B = {};
+  for (int o = 0; o < 9; ++o)
+    for (int c = 0; c < 9; ++c)
+      B.v[o][c] = ((o >= 1 && c >= 1) ? M[o - 1][c - 1] : 0.0) - ((o <= 7 && c <= 7) ? M[o][c] : 0.0);
+  return B;
+}
+constexpr Mat9 SMC_B = smc_face_matrix();
+
+template <bool FIXED>
+__device__ __forceinline__ void bvec(const DevMech *__restrict__ m, const double *u, double *v) {
+#pragma unroll
+  for (int o = 0; o < 9; ++o) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = (o > 4 ? o - 4 : 0); c <= (o < 4 ? o + 4 : 8); ++c)
+      acc += (FIXED ? SMC_B.v[o][c] : m->B[o][c]) * u[c];
+    v[o] = acc;
   }
 }
-// (H_{i+1/2} - H_{i-1/2}) / dx^2 with H = sum_m a_{i+m} (row sum m)
-__device__ __forceinline__ double narrow(const double *a, const Rows &R, double idx2) {
-  double hp = 0.0, hm = 0.0;
+__device__ __forceinline__ double dot9(const double *a, const double *v) {
+  double s = 0.0;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    hp += a[1 + r] * R.p[r];
-    hm += a[r] * R.m[r];
-  }
-  return (hp - hm) * idx2;
+  for (int o = 0; o < 9; ++o) s += a[o] * v[o];
+  return s;
+}
+// first derivative of the pointwise product a*b
+__device__ __forceinline__ double d1p(const double *a, const double *b, double idx) {
+  return (C1 * (a[5] * b[5] - a[3] * b[3]) + C2 * (a[6] * b[6] - a[2] * b[2]) +
+          C3 * (a[7] * b[7] - a[1] * b[1]) + C4 * (a[8] * b[8] - a[0] * b[0])) * idx;
 }
 
-template <int NS, int D>
-__global__ __launch_bounds__(256) void k_dir(const BoxDev *__restrict__ boxes,
+template <int NS, int D, bool FIXED>
+__global__ __launch_bounds__(256, 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
                                              TileShape ts, FRef Uref,
                                              const double *__restrict__ Pbase,
@@ -385,16 +418,19 @@ __global__ __launch_bounds__(256) void k_dir(const BoxDev *__restrict__ boxes,
                                              unsigned parts, const DevMech *__restrict__ m) {
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
+  constexpr int J1 = D == 0 ? 1 : 0, J2 = D == 2 ? 1 : 2;   // the two other directions
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
     int x, y, z;
     tile_cell(w, ts, x, y, z);
     if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    // per-lane cell indices are 32-bit; everything uniform (field bases,
+    // stencil offsets) goes into the 64-bit base of each load
     const long long nS = (long long)b.sx * b.sy * b.sz;
     const long long nI = (long long)b.nx * b.ny * b.nz;
-    const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
-    const long long i = ((long long)z * b.ny + y) * b.nx + x;
+    const unsigned s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+    const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
     const long long st = D == 0 ? 1 : (D == 1 ? (long long)b.sx : (long long)b.sx * b.sy);
     const double *U = Uref.get(w.box, b.offS * NU);
     const double *P = Pbase + b.offS * NP;
@@ -406,164 +442,136 @@ __global__ __launch_bounds__(256) void k_dir(const BoxDev *__restrict__ boxes,
     for (int q = 0; q < NU; ++q) acc[q] = 0.0;
     auto line = [&](const double *f, double *v) {
 #pragma unroll
-      for (int o = 0; o < 9; ++o) v[o] = f[s + (o - 4) * st];
+      for (int o = 0; o < 9; ++o) v[o] = (f + (o - 4) * st)[s];
     };
     double ud[9], pp[9];
     line(P + (L::PU + D) * nS, ud);
     line(P + L::PP * nS, pp);
 
     if (parts & 1) {  // convective terms -D_D(F_D(U))
-      double f[9], Uq[9];
+      double f[9];
       line(U + (1 + D) * nS, f);
       acc[0] -= d1(f, idx);
 #pragma unroll
       for (int ic = 0; ic < 3; ++ic) {
-        line(U + (1 + ic) * nS, Uq);
+        line(U + (1 + ic) * nS, f);
 #pragma unroll
-        for (int o = 0; o < 9; ++o) f[o] = Uq[o] * ud[o] + (ic == D ? pp[o] : 0.0);
+        for (int o = 0; o < 9; ++o) f[o] = f[o] * ud[o] + (ic == D ? pp[o] : 0.0);
         acc[1 + ic] -= d1(f, idx);
       }
-      line(U + 4 * nS, Uq);
+      line(U + 4 * nS, f);
 #pragma unroll
-      for (int o = 0; o < 9; ++o) f[o] = (Uq[o] + pp[o]) * ud[o];
-      acc[4] -= d1(f, idx);
-#pragma unroll
+      for (int o = 0; o < 9; ++o) f[o] += pp[o];
+      acc[4] -= d1p(f, ud, idx);
+#pragma unroll 1
       for (int k = 0; k < NS; ++k) {
-        line(U + (5 + k) * nS, Uq);
-#pragma unroll
-        for (int o = 0; o < 9; ++o) f[o] = Uq[o] * ud[o];
-        acc[5 + k] -= d1(f, idx);
+        line(U + (5 + k) * nS, f);
+        acc[5 + k] -= d1p(f, ud, idx);
       }
     }
 
     if (parts & 2) {  // diffusive terms
       const double bulk = m->bulk;
-      double mu[9], a[9], v[9], vel[3][9];
-      Rows R;
-      line(P + L::PMU * nS, mu);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) line(P + (L::PU + c) * nS, vel[c]);
-      // viscous momentum: L_D(a, u_i), a = 4/3 mu + xi along i = D, mu otherwise
-#pragma unroll
-      for (int ic = 0; ic < 3; ++ic) {
-#pragma unroll
-        for (int o = 0; o < 9; ++o) a[o] = ic == D ? (4.0 / 3.0 + bulk) * mu[o] : mu[o];
-        rows(m, vel[ic], R);
-        acc[1 + ic] += narrow(a, R, idx2);
-      }
-      // heat conduction L_D(lambda, T)
-      line(P + L::PLAM * nS, a);
-      line(P + L::PT * nS, v);
-      rows(m, v, R);
-      acc[4] += narrow(a, R, idx2);
-      // viscous work: L_D(mu, |u|^2/2) + L_D(mu/3 + xi, u_D^2/2)
-#pragma unroll
-      for (int o = 0; o < 9; ++o)
-        v[o] = 0.5 * (vel[0][o] * vel[0][o] + vel[1][o] * vel[1][o] + vel[2][o] * vel[2][o]);
-      rows(m, v, R);
-      acc[4] += narrow(mu, R, idx2);
-#pragma unroll
-      for (int o = 0; o < 9; ++o) {
-        v[o] = 0.5 * ud[o] * ud[o];
-        a[o] = (1.0 / 3.0 + bulk) * mu[o];
-      }
-      rows(m, v, R);
-      acc[4] += narrow(a, R, idx2);
-      // mixed terms: D_D(mu D_i u_D) (i != D), D_D((xi - 2/3 mu) sum_{j!=D} D_j u_j),
-      // D_D(mu sum_{j!=D} u_j D_j u_D + (xi - 2/3 mu) u_D sum_{j!=D} D_j u_j)
+      const double lam2 = bulk - 2.0 / 3.0;
       {
-        constexpr int J1 = D == 0 ? 1 : 0, J2 = D == 2 ? 1 : 2;
-        double g1D[9], g2D[9], dsum[9], f[9];
-        line(G + (3 * J1 + D) * nS, g1D);
-        line(G + (3 * J2 + D) * nS, g2D);
-        line(G + (3 * J1 + J1) * nS, a);
-        line(G + (3 * J2 + J2) * nS, v);
+        double mu[9], ke[9], fe[9], u9[9], v[9], g[9];
+        line(P + L::PMU * nS, mu);
 #pragma unroll
-        for (int o = 0; o < 9; ++o) dsum[o] = a[o] + v[o];
+        for (int o = 0; o < 9; ++o) ke[o] = fe[o] = 0.0;
 #pragma unroll
-        for (int o = 0; o < 9; ++o) f[o] = mu[o] * g1D[o];
-        acc[1 + J1] += d1(f, idx);
+        for (int ic = 0; ic < 3; ++ic) {
+          line(P + (L::PU + ic) * nS, u9);
+          // viscous stress, second-derivative part: L_D(a, u_ic),
+          // a = (4/3 mu + xi) along D, mu across
+          bvec<FIXED>(m, u9, v);
+          acc[1 + ic] += (ic == D ? 4.0 / 3.0 + bulk : 1.0) * dot9(mu, v) * idx2;
 #pragma unroll
-        for (int o = 0; o < 9; ++o) f[o] = mu[o] * g2D[o];
-        acc[1 + J2] += d1(f, idx);
+          for (int o = 0; o < 9; ++o) ke[o] += 0.5 * u9[o] * u9[o];
+          if (ic == D) {
+            // D_D((xi - 2/3 mu) sum_{j!=D} D_j u_j) and its viscous-work part
+            line(G + (3 * J1 + J1) * nS, g);
+            line(G + (3 * J2 + J2) * nS, v);
 #pragma unroll
-        for (int o = 0; o < 9; ++o) f[o] = (bulk - 2.0 / 3.0) * mu[o] * dsum[o];
-        acc[1 + D] += d1(f, idx);
+            for (int o = 0; o < 9; ++o) {
+              g[o] = lam2 * mu[o] * (g[o] + v[o]);
+              fe[o] += u9[o] * g[o];
+            }
+            acc[1 + D] += d1(g, idx);
+            // viscous work L_D(mu/3 + xi, u_D^2 / 2)
 #pragma unroll
-        for (int o = 0; o < 9; ++o)
-          f[o] = mu[o] * (vel[J1][o] * g1D[o] + vel[J2][o] * g2D[o]) +
-                 (bulk - 2.0 / 3.0) * mu[o] * vel[D][o] * dsum[o];
-        acc[4] += d1(f, idx);
-      }
-      // species diffusion with the correction velocity (direction-D share)
-      {
-        double rd[9], ep[9], Rpp[8], Rpm[8];
-        line(P + L::PRD * nS, rd);
-        rows(m, pp, R);
+            for (int o = 0; o < 9; ++o) g[o] = 0.5 * u9[o] * u9[o];
+            bvec<FIXED>(m, g, v);
+            acc[4] += (1.0 / 3.0 + bulk) * dot9(mu, v) * idx2;
+          } else {
+            // D_D(mu D_ic u_D) and its viscous-work part mu u_ic D_ic u_D
+            line(G + (3 * ic + D) * nS, g);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          Rpp[r] = R.p[r];
-          Rpm[r] = R.m[r];
+            for (int o = 0; o < 9; ++o) {
+              g[o] *= mu[o];
+              fe[o] += u9[o] * g[o];
+            }
+            acc[1 + ic] += d1(g, idx);
+          }
         }
-        const double Dp = d1(pp, idx);
-        const double ip = 1.0 / pp[4];
+        // viscous work L_D(mu, |u|^2/2) and the first-derivative part
+        bvec<FIXED>(m, ke, v);
+        acc[4] += dot9(mu, v) * idx2 + d1(fe, idx);
+        // heat conduction L_D(lambda, T)
+        line(P + L::PT * nS, u9);
+        bvec<FIXED>(m, u9, v);
+        line(P + L::PLAM * nS, g);
+        acc[4] += dot9(g, v) * idx2;
+      }
+      // species diffusion (pairs (rho D_k, X_k), (rho D_k (X_k-Y_k)/p, p) and
+      // the energy pairs with h_k) and the correction velocity V_c,D, div V_c
+      {
+        double rd[9], wp[9], u9[9], v[9], g[9];
+        line(P + L::PRD * nS, rd);
+        bvec<FIXED>(m, pp, v);
 #pragma unroll
-        for (int o = 0; o < 9; ++o) ep[o] = 0.0;
+        for (int o = 0; o < 9; ++o) wp[o] = rd[o] * v[o] / pp[o];
+        const double Dpp = d1(pp, idx) / pp[4];
+        const double rd4 = rd[4];
         double divVc = 0.0, Vc = 0.0;
-        double DY[NS], DhY[NS], Yc[NS], hc[NS];
-#pragma unroll
+#pragma unroll 1
         for (int k = 0; k < NS; ++k) {
           const double iLe = m->invLe[k];
-          double X[9], Yv[9], h[9], ad[9], ap[9], f[9];
-          line(P + (L::PX + k) * nS, X);
-          line(P + (L::PY + k) * nS, Yv);
-          line(P + (L::PH + k) * nS, h);
+          line(P + (L::PX + k) * nS, u9);
+          bvec<FIXED>(m, u9, v);
+          const double DX = d1(u9, idx);
+          line(P + (L::PY + k) * nS, g);
+          const double dXY4 = u9[4] - g[4];
+#pragma unroll
+          for (int o = 0; o < 9; ++o) u9[o] -= g[o];
+          const double Lp = dot9(u9, wp);
+          const double Lx = dot9(rd, v);
+          line(P + (L::PH + k) * nS, g);
+          double LhX = 0.0, Lpe = 0.0;
 #pragma unroll
           for (int o = 0; o < 9; ++o) {
-            ad[o] = rd[o] * iLe;
-            ap[o] = ad[o] * (X[o] - Yv[o]) / pp[o];
-            ep[o] += ap[o] * h[o];
+            LhX += rd[o] * g[o] * v[o];
+            Lpe += u9[o] * g[o] * wp[o];
           }
-          rows(m, X, R);
-          const double Lx = narrow(ad, R, idx2);
-          Rows Rp;
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            Rp.p[r] = Rpp[r];
-            Rp.m[r] = Rpm[r];
-          }
-          const double Lp = narrow(ap, Rp, idx2);
-          acc[5 + k] += Lx + Lp;
-          divVc -= Lx + Lp;
-#pragma unroll
-          for (int o = 0; o < 9; ++o) f[o] = ad[o] * h[o];
-          acc[4] += narrow(f, R, idx2);
-          Vc -= ad[4] * (d1(X, idx) + (X[4] - Yv[4]) * Dp * ip);
-          DY[k] = d1(Yv, idx);
-#pragma unroll
-          for (int o = 0; o < 9; ++o) f[o] = h[o] * Yv[o];
-          DhY[k] = d1(f, idx);
-          Yc[k] = Yv[4];
-          hc[k] = h[4];
+          const double t = iLe * (Lx + Lp) * idx2;
+          acc[5 + k] += t;
+          divVc -= t;
+          acc[4] += iLe * (LhX + Lpe) * idx2;
+          Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
         }
-        {
-          Rows Rp;
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            Rp.p[r] = Rpp[r];
-            Rp.m[r] = Rpm[r];
-          }
-          acc[4] += narrow(ep, Rp, idx2);
-        }
-#pragma unroll
+        // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart with h_k Y_k
+#pragma unroll 1
         for (int k = 0; k < NS; ++k) {
-          acc[5 + k] += Yc[k] * divVc + Vc * DY[k];
-          acc[4] += hc[k] * Yc[k] * divVc + Vc * DhY[k];
+          line(P + (L::PY + k) * nS, u9);
+          line(P + (L::PH + k) * nS, g);
+          const double DY = d1(u9, idx);
+          const double DhY = d1p(g, u9, idx);
+          acc[5 + k] += u9[4] * divVc + Vc * DY;
+          acc[4] += g[4] * u9[4] * divVc + Vc * DhY;
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < NU; ++q) F[q * nI + i] += acc[q];
+    for (int q = 0; q < NU; ++q) (F + q * nI)[i] += acc[q];
   }
 }
 
@@ -629,16 +637,68 @@ __global__ __launch_bounds__(256) void k_sdc_node(const BoxDev *__restrict__ box
   }
 }
 
-// One coarse interval of the multirate sweep, mode 1 (eq. mrupdate), all
-// fine sub-steps of the interval for one cell in registers:
+// One coarse interval of the multirate sweep, mode 1 (eq. mrupdate):
 //   U_{q+1} = U_q + dtau_q [f1(U^{k+1}_p) - f1(U^k_p)] + dtau_q [f2(U^{k+1}_q) - f2(U^k_q)]
 //             + dt S22_q . F2^k + dt S21_q . F1^k,
-// with f2 the chemistry (species components only) evaluated here.
+// f2 the chemistry (species components only).  Everything except the
+// f2(U^{k+1}_q) term is known before the interval starts; k_mr_src forms it
+// for all fine sub-steps of the interval (a streaming pass over the node
+// values) into A[q][component], and k_mr_step then runs the sub-steps of a
+// cell in registers: Newton, chemistry, U += A[q] + dtau_q f2.
 template <int NS>
-__global__ __launch_bounds__(256) void k_mr_fine(const BoxDev *__restrict__ boxes,
+__global__ __launch_bounds__(256) void k_mr_src(const BoxDev *__restrict__ boxes,
+                                                const Item *__restrict__ items, int nitems,
+                                                TileShape ts, const FineCoef *__restrict__ fc,
+                                                FinePtrs fp, double *__restrict__ Abase,
+                                                long long aslot) {
+  constexpr int NU = 5 + NS;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    const long long nI = (long long)b.nx * b.ny * b.nz;
+    const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
+    const long long o1 = b.offI * NU, o2 = b.offI * NS;
+    auto F1 = [&](int slot, int q) { return fp.F1base + (slot * fp.f1slot + o1 + q * nI); };
+    auto F2 = [&](int slot, int k) { return fp.F2base + (slot * fp.f2slot + o2 + k * nI); };
+    auto A = [&](int r, int q) { return Abase + (r * aslot + o1 + q * nI); };
+    const int n1 = fc->n1, nq = fc->nq, nf = fc->nfine;
+    const double dt = fp.dt;
+#pragma unroll 1
+    for (int q = 0; q < NU; ++q) {
+      double f1[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) f1[j] = j < n1 ? F1(fp.F1old[j], q)[i] : 0.0;
+      const double dF1 = F1(fp.F1new_p, q)[i] - F1(fp.F1old_p, q)[i];
+#pragma unroll 1
+      for (int r = 0; r < nq; ++r) {
+        const double dtq = fc->dtq[r] * dt;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += fc->S21[r][j] * f1[j];
+        double v = dtq * dF1 + dt * acc;
+        if (q >= 5) {
+          const int k = q - 5, jlo = fc->jlo[r];
+          double s22 = 0.0;
+#pragma unroll
+          for (int j = 0; j < 9; ++j)
+            if (j < nf) s22 += fc->S22[r][j] * F2(fp.F2old[jlo + j], k)[i];
+          v += dt * s22 - dtq * F2(fp.F2old[r], k)[i];
+        }
+        A(r, q)[i] = v;
+      }
+    }
+  }
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxes,
                                                  const Item *__restrict__ items, int nitems,
                                                  TileShape ts, FRef Uin, FRef Uout,
                                                  const FineCoef *__restrict__ fc, FinePtrs fp,
+                                                 const double *__restrict__ Abase, long long aslot,
                                                  const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -648,56 +708,47 @@ __global__ __launch_bounds__(256) void k_mr_fine(const BoxDev *__restrict__ boxe
     tile_cell(w, ts, x, y, z);
     if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
     const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
-    const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
-    const long long i = ((long long)z * b.ny + y) * b.nx + x;
+    const unsigned s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+    const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
     const long long o1 = b.offI * NU, o2 = b.offI * NS;
+    auto F2 = [&](int slot, int k) { return fp.F2base + (slot * fp.f2slot + o2 + k * nI); };
+    auto A = [&](int r, int q) { return Abase + (r * aslot + o1 + q * nI); };
     const double *Ui = Uin.get(w.box, b.offS * NU);
     double *Uo = Uout.get(w.box, b.offS * NU);
     double Uc[NU];
 #pragma unroll
-    for (int q = 0; q < NU; ++q) Uc[q] = Ui[q * nS + s];
-    const int n1 = fc->n1, nq = fc->nq;
-    const double dt = fp.dt;
+    for (int q = 0; q < NU; ++q) Uc[q] = (Ui + q * nS)[s];
+    const int nq = fc->nq;
     int errs = 0;
+    // the temperature of the previous sub-step seeds the next Newton solve
+    double Tprev = 1000.0;
     for (int qq = 0; qq < nq; ++qq) {
       double f2[NS];
       if (qq == 0 && fp.q0_known) {
 #pragma unroll
-        for (int k = 0; k < NS; ++k) f2[k] = fp.F2old[0][o2 + k * nI + i];
+        for (int k = 0; k < NS; ++k) f2[k] = F2(fp.F2old[0], k)[i];
       } else {
         double rho, u[3], Y[NS], T;
-        errs |= cell_state<NS>(m, Uc, rho, u, Y, T);
+        errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
+        Tprev = T;
         production<NS>(m, rho, T, Y, f2);
 #pragma unroll
-        for (int k = 0; k < NS; ++k) fp.F2new[qq][o2 + k * nI + i] = f2[k];
+        for (int k = 0; k < NS; ++k) F2(fp.F2new[qq], k)[i] = f2[k];
       }
-      const double dtq = fc->dtq[qq] * dt;
+      const double dtq = fc->dtq[qq] * fp.dt;
 #pragma unroll
-      for (int q = 0; q < NU; ++q) {
-        const long long qi = o1 + q * nI + i;
-        double s21 = 0.0;
-        for (int j = 0; j < n1; ++j) s21 += fc->S21[qq][j] * fp.F1old[j][qi];
-        double du = dtq * (fp.F1new_p[qi] - fp.F1old_p[qi]) + dt * s21;
-        if (q >= 5) {
-          const int k = q - 5;
-          const long long ki = o2 + k * nI + i;
-          double s22 = 0.0;
-          for (int j = 0; j <= nq; ++j) s22 += fc->S22[qq][j] * fp.F2old[j][ki];
-          du += dtq * (f2[k] - fp.F2old[qq][ki]) + dt * s22;
-        }
-        Uc[q] += du;
-      }
+      for (int q = 0; q < NU; ++q) Uc[q] += A(qq, q)[i] + (q >= 5 ? dtq * f2[q - 5] : 0.0);
     }
     if (fp.eval_last) {
       double rho, u[3], Y[NS], T, f2[NS];
-      errs |= cell_state<NS>(m, Uc, rho, u, Y, T);
+      errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
       production<NS>(m, rho, T, Y, f2);
 #pragma unroll
-      for (int k = 0; k < NS; ++k) fp.F2new[nq][o2 + k * nI + i] = f2[k];
+      for (int k = 0; k < NS; ++k) F2(fp.F2new[nq], k)[i] = f2[k];
     }
     if (errs) atomicOr(err, errs);
 #pragma unroll
-    for (int q = 0; q < NU; ++q) Uo[q * nS + s] = Uc[q];
+    for (int q = 0; q < NU; ++q) (Uo + q * nS)[s] = Uc[q];
   }
 }
 
@@ -737,20 +788,28 @@ struct Launch {
                        c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, G);
     prof_end(c.prof, K_VGRAD, c.stream);
   }
-  static void dir(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F,
-                  unsigned parts) {
+  template <bool FIXED>
+  static void dir_t(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F,
+                    unsigned parts) {
     const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
     prof_begin(c.prof, K_DIR_X + d, c.stream);
     if (d == 0)
-      hipLaunchKernelGGL((k_dir<NS, 0>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P, G, F,
-                         parts, c.mech);
+      hipLaunchKernelGGL((k_dir<NS, 0, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P,
+                         G, F, parts, c.mech);
     else if (d == 1)
-      hipLaunchKernelGGL((k_dir<NS, 1>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P, G, F,
-                         parts, c.mech);
+      hipLaunchKernelGGL((k_dir<NS, 1, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P,
+                         G, F, parts, c.mech);
     else
-      hipLaunchKernelGGL((k_dir<NS, 2>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P, G, F,
-                         parts, c.mech);
+      hipLaunchKernelGGL((k_dir<NS, 2, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P,
+                         G, F, parts, c.mech);
     prof_end(c.prof, K_DIR_X + d, c.stream);
+  }
+  static void dir(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F,
+                  unsigned parts) {
+    if (c.smc_stencil)
+      dir_t<true>(c, d, U, P, G, F, parts);
+    else
+      dir_t<false>(c, d, U, P, G, F, parts);
   }
   static void chem(const LaunchCtx &c, FRef U, double *F2) {
     prof_begin(c.prof, K_CHEM, c.stream);
@@ -765,10 +824,14 @@ struct Launch {
     prof_end(c.prof, K_SDC_NODE, c.stream);
   }
   static void mr_fine(const LaunchCtx &c, FRef Uin, FRef Uout, const FineCoef *fc,
-                      const FinePtrs &fp) {
+                      const FinePtrs &fp, double *A, long long aslot) {
+    const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
+    prof_begin(c.prof, K_MR_SRC, c.stream);
+    hipLaunchKernelGGL(k_mr_src<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, fc, fp, A, aslot);
+    prof_end(c.prof, K_MR_SRC, c.stream);
     prof_begin(c.prof, K_MR_FINE, c.stream);
-    hipLaunchKernelGGL(k_mr_fine<NS>, dim3(grid_for(c.nI, c.cap)), dim3(c.tsI.tx * c.tsI.ty * c.tsI.tz), 0,
-                       c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc, fp, c.mech, c.err);
+    hipLaunchKernelGGL(k_mr_step<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
+                       fp, A, aslot, c.mech, c.err);
     prof_end(c.prof, K_MR_FINE, c.stream);
   }
 };

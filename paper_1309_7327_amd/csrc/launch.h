@@ -9,7 +9,7 @@ namespace nsdc {
 // Kernel identities for the per-kernel timers.
 enum KernelId {
   K_PRIM_TO_CONS = 0, K_GHOST, K_PRIMS, K_VGRAD, K_DIR_X, K_DIR_Y, K_DIR_Z, K_CHEM, K_SDC_NODE,
-  K_MR_FINE, K_NKERNELS
+  K_MR_FINE, K_MR_SRC, K_NKERNELS
 };
 struct Profiler;
 // Record a HIP event on `s` before (begin) / after (end) a launch of kernel `id`
@@ -30,6 +30,7 @@ struct LaunchCtx {
   const DevMech *mech;
   int *err;
   Profiler *prof;
+  bool smc_stencil;   // the default narrow-stencil parameters: compile-time B
 };
 
 struct Ops {
@@ -42,7 +43,7 @@ struct Ops {
   void (*dir)(const LaunchCtx &, int, FRef, const double *, const double *, FRef, unsigned);
   void (*chem)(const LaunchCtx &, FRef, double *);
   void (*sdc_node)(const LaunchCtx &, FRef, FRef, const NodeArgs &);
-  void (*mr_fine)(const LaunchCtx &, FRef, FRef, const FineCoef *, const FinePtrs &);
+  void (*mr_fine)(const LaunchCtx &, FRef, FRef, const FineCoef *, const FinePtrs &, double *, long long);
 };
 
 // nullptr for an unsupported species count

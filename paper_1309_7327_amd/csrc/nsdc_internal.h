@@ -31,6 +31,7 @@ struct DevMech {
   int rs[NSDC_NRMAX][2], ps[NSDC_NRMAX][2];
   int dnu[NSDC_NRMAX];
   double M[8][8];             // narrow-stencil matrix, [m+3][n+3]
+  double B[9][9];             // face-difference matrix B_oc = M_{o-1,c-1} - M_{o,c}
 };
 
 // One box of a batch.  offS / offI: offsets (in cells) of this box inside
@@ -76,18 +77,25 @@ struct NodeArgs {
 // nodes, and the fine sub-step lengths (device memory, one per interval).
 struct FineCoef {
   double S21[NSDC_MAXFINE][8];
-  double S22[NSDC_MAXFINE][NSDC_MAXFINE];
+  double S22[NSDC_MAXFINE][9];   // row q over the nodes jlo[q] .. jlo[q] + nfine - 1 of its piece
   double dtq[NSDC_MAXFINE];
+  int jlo[NSDC_MAXFINE];
   int n1;          // coarse nodes M1 + 1
   int nq;          // fine sub-steps in the interval
+  int nfine;       // nodes of one fine polynomial piece
 };
 
-// Node arrays of one coarse interval (passed by value; arena bases).
+// Node arrays of one coarse interval (passed by value).  Node values live
+// in two arenas (f1: nU components, f2: ns components) of equal-size slots;
+// the roles of the slots change from sweep to sweep, so the kernel receives
+// slot numbers rather than pointers.
 struct FinePtrs {
-  const double *F1old[8];              // f1 at the coarse nodes, iteration k
-  const double *F1new_p, *F1old_p;     // f1 at the interval's left coarse node, k+1 and k
-  const double *F2old[NSDC_MAXFINE];   // f2 at the interval's fine nodes, iteration k
-  double *F2new[NSDC_MAXFINE];         // f2 at the interval's fine nodes, iteration k+1
+  double *F1base, *F2base;             // arena bases
+  long long f1slot, f2slot;            // doubles per slot
+  unsigned short F1old[8];              // f1 at the coarse nodes, iteration k
+  unsigned short F1new_p, F1old_p;      // f1 at the interval's left coarse node, k+1 and k
+  unsigned short F2old[NSDC_MAXFINE];   // f2 at the interval's fine nodes, iteration k
+  unsigned short F2new[NSDC_MAXFINE];   // f2 at the interval's fine nodes, iteration k+1
   int q0_known;    // f2 at the first fine node is the step-start value F2old[0]
   int eval_last;   // evaluate and store f2 at the interval's last fine node
   double dt;

@@ -177,3 +177,23 @@ def test_sampled_cells_of_full_size_rhs():
     ok, rep = G.compare(got.T, ref.T, floor)
     print(G.fmt(rep))
     assert ok, G.fmt(rep)
+
+
+@pytest.mark.parametrize("params", [(0.0, 0.0), (1059283 / 13608000, -856481 / 40824000)])
+def test_rhs_eval_other_stencil_parameters(params):
+    """Non-default (m47, m48) take the runtime-matrix path of the kernels."""
+    m = dict(mechanism.load("mech9le"))
+    m["m47"], m["m48"] = params
+    om = oracle.Mechanism(m)
+    ctx = N.Context(0)
+    ctx.set_mechanism(m)
+    shape, dx = (10, 9, 12), 1e-4
+    prim = fields.sines(shape, dx, m["ns"], 17)
+    bx, U = G.device_state(ctx, prim, dx)
+    F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
+    ctx.rhs_eval(bx, U, F, N.RHS_DIFF)
+    ctx.check_status()
+    fref, floor = G.ulp_floor(lambda V: oracle.rhs(om, V, dx, parts=oracle.DIFF), oracle.prim_to_cons(om, prim))
+    ok, rep = G.compare(G.host(F), fref, floor)
+    print(params, G.fmt(rep))
+    assert ok, G.fmt(rep)
