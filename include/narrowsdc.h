@@ -134,6 +134,24 @@ int sdc_step_batched(sdc_context *ctx, int nbox, const box_desc *boxes, double *
                      double dt, int nsteps, const sdc_scheme *scheme, void *workspace,
                      size_t ws_bytes, void *stream);
 
+/* Graph mode (enable != 0): sdc_step / sdc_step_batched on a non-null stream
+ * capture all launches of a call into a HIP graph the first time and replay
+ * it for calls with identical arguments (same boxes, state pointers, dt,
+ * nsteps, scheme and workspace).  Capture allocates the graph; replays
+ * allocate nothing.  Disabling frees the cached graphs. */
+int sdc_set_graph(sdc_context *ctx, int enable);
+
+/* Tile-shape autotuner for a box set: times one full right-hand-side
+ * evaluation over all boxes for each candidate workgroup tile shape and
+ * persistent-grid size, and keeps the fastest for later calls on boxes of
+ * these dimensions.  U[i]: the boxes' ghosted states (device; ghosts are
+ * refilled, interiors untouched).  workspace: device scratch of at least
+ * the sdc_workspace_size of a single-rate scheme for these boxes.  choice
+ * (may be null) receives tile x, y, z and the workgroup cap (0 = one
+ * workgroup per tile).  Results do not depend on the choice. */
+int sdc_autotune(sdc_context *ctx, int nbox, const box_desc *boxes, double *const *U,
+                 void *workspace, size_t ws_bytes, void *stream, int *choice);
+
 /* Synchronise `stream`, return and clear the device error word (SDC_OK or
  * SDC_ETEMP). */
 int last_status(sdc_context *ctx, void *stream);

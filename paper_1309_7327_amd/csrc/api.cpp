@@ -113,6 +113,7 @@ struct Plan {
   Item *d_items = nullptr;   // interior, stored, ghost lists back to back
   int nI = 0, nS = 0, nG = 0;
   TileShape tsI{}, tsS{};
+  int cap = 0;                 // workgroups per launch (0: one per work item)
   double **d_Utab = nullptr;
   std::vector<double *> Uptrs;
   ~Plan() {
@@ -209,6 +210,16 @@ struct sdc_context {
   int grid_cap = 0;
   std::unique_ptr<Profiler> prof;
   bool smc_stencil = false;
+  // autotuned launch shapes per box set (dimensions only)
+  struct Tuned {
+    TileShape tI, tS;
+    int cap;
+  };
+  std::map<std::string, Tuned> tuned;
+  int n_cu = 0;
+  // captured step graphs
+  bool use_graph = false;
+  std::map<std::string, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -235,11 +246,29 @@ int check_box(sdc_context *c, const box_desc *b) {
 }
 
 // Build (or fetch) the work plan of a set of boxes.
+std::string box_signature(int nbox, const box_desc *b) {
+  std::string k;
+  char buf[64];
+  for (int i = 0; i < nbox; ++i) {
+    snprintf(buf, sizeof buf, "%d,%d,%d;", b[i].nx, b[i].ny, b[i].nz);
+    k += buf;
+  }
+  return k;
+}
+
 int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Plan **out) {
   TileShape tI{}, tS{};
+  // batches run as persistent launches: a few workgroups per compute unit
+  // walk the (box, tile) list
+  int cap = nbox > 1 ? 4 * std::max(c->n_cu, 1) : 0;
+  auto tu = c->forceI.tx ? c->tuned.end() : c->tuned.find(box_signature(nbox, bx));
   if (c->forceI.tx) {
     tI = c->forceI;
     tS = c->forceS;
+  } else if (tu != c->tuned.end()) {
+    tI = tu->second.tI;
+    tS = tu->second.tS;
+    cap = tu->second.cap;
   } else {
     int mx = 0, my = 0, mz = 0;
     for (int i = 0; i < nbox; ++i) {
@@ -251,18 +280,19 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
     tI = default_tile(mx, my, mz);
     tS = default_tile(nbox > 1 ? 16 : mx + 8, my + 8, mz + 8);
   }
-  std::string key = plan_key(nbox, bx, U, tI, tS);
+  std::string key = plan_key(nbox, bx, U, tI, tS) + "|cap" + std::to_string(cap);
   auto it = c->plans.find(key);
   if (it != c->plans.end()) {
     *out = it->second.get();
     return SDC_OK;
   }
-  if (c->plans.size() > 32) c->plans.clear();
+  if (c->plans.size() > 512) c->plans.clear();
   auto p = std::make_unique<Plan>();
   p->nbox = nbox;
   p->boxes.assign(bx, bx + nbox);
   p->tsI = tI;
   p->tsS = tS;
+  p->cap = cap;
   std::vector<BoxDev> hb(nbox);
   std::vector<Item> iI, iS, iG;
   for (int b = 0; b < nbox; ++b) {
@@ -320,7 +350,7 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.nG = p->nG;
   l.tsI = p->tsI;
   l.tsS = p->tsS;
-  l.cap = c->grid_cap > 0 ? c->grid_cap : 1 << 30;
+  l.cap = c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : 1 << 30);
   l.mech = c->d_mech;
   l.err = c->d_err;
   l.prof = c->prof.get();
@@ -585,6 +615,8 @@ int sdc_context_create(sdc_context **out, int device) {
   if (hipSetDevice(device) != hipSuccess) return SDC_EHIP;
   auto *c = new sdc_context();
   c->device = device;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    c->n_cu = 256;
   if (hipMalloc(&c->d_err, sizeof(int)) != hipSuccess || hipMemset(c->d_err, 0, sizeof(int)) != hipSuccess ||
       hipMalloc(&c->d_mech, sizeof(DevMech)) != hipSuccess) {
     delete c;
@@ -598,6 +630,8 @@ int sdc_context_destroy(sdc_context *c) {
   if (!c) return SDC_EINVAL;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  c->graphs.clear();
   c->plans.clear();
   if (c->d_err) (void)hipFree(c->d_err);
   if (c->d_mech) (void)hipFree(c->d_mech);
@@ -763,6 +797,62 @@ int sdc_workspace_size(const sdc_context *c, int nbox, const box_desc *boxes,
   return SDC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Run (or replay) one sdc_step call.  With graphs enabled and a non-null
+// stream the launches of the whole call are captured once into a HIP graph,
+// keyed by everything they depend on, and replayed on identical calls.
+int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U, double dt,
+               int nsteps, const sdc_scheme *scheme, void *workspace, size_t ws_bytes,
+               hipStream_t stream) {
+  Plan *pl;
+  int rc = get_plan(c, nbox, boxes, nbox > 1 ? U : nullptr, &pl);
+  if (rc) return rc;
+  FRef Uref = nbox > 1 ? FRef{nullptr, pl->d_Utab} : FRef{U[0], nullptr};
+  if (scheme->n_fine != 0) {
+    rc = fine_tables(c, scheme);
+    if (rc) return rc;
+  }
+  if (!c->use_graph || !stream || c->prof) {
+    rc = run_sdc(c, pl, Uref, dt, nsteps, scheme, workspace, ws_bytes, stream);
+    if (rc) return rc;
+    HIPCHECK(c, hipGetLastError());
+    return SDC_OK;
+  }
+  char buf[256];
+  snprintf(buf, sizeof buf, "|%p|%.17g|%d|%d,%d,%d,%d|%p|%zu|%p", (void *)pl, dt, nsteps, scheme->n_coarse,
+           scheme->sweeps, scheme->n_fine, scheme->fine_repeat, workspace, ws_bytes,
+           nbox > 1 ? nullptr : (void *)U[0]);
+  const std::string key = buf;
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (c->graphs.size() >= 8) {
+      for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+      c->graphs.clear();
+    }
+    HIPCHECK(c, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    rc = run_sdc(c, pl, Uref, dt, nsteps, scheme, workspace, ws_bytes, stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(c, SDC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, SDC_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    it = c->graphs.emplace(key, exec).first;
+  }
+  HIPCHECK(c, hipGraphLaunch(it->second, stream));
+  return SDC_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int sdc_step(sdc_context *c, const box_desc *box, double *U, double dt, int nsteps,
              const sdc_scheme *scheme, void *workspace, size_t ws_bytes, void *stream) {
   if (!c) return SDC_EINVAL;
@@ -774,13 +864,8 @@ int sdc_step(sdc_context *c, const box_desc *box, double *U, double dt, int nste
   if (!U) return fail(c, SDC_EINVAL, "null state");
   if (!(dt > 0) || nsteps < 1) return fail(c, SDC_EINVAL, "dt must be > 0 and nsteps >= 1");
   HIPCHECK(c, hipSetDevice(c->device));
-  Plan *pl;
-  rc = get_plan(c, 1, box, nullptr, &pl);
-  if (rc) return rc;
-  rc = run_sdc(c, pl, FRef{U, nullptr}, dt, nsteps, scheme, workspace, ws_bytes, (hipStream_t)stream);
-  if (rc) return rc;
-  HIPCHECK(c, hipGetLastError());
-  return SDC_OK;
+  double *Ut[1] = {U};
+  return step_entry(c, 1, box, Ut, dt, nsteps, scheme, workspace, ws_bytes, (hipStream_t)stream);
 }
 
 int sdc_step_batched(sdc_context *c, int nbox, const box_desc *boxes, double *const *U, double dt,
@@ -798,12 +883,91 @@ int sdc_step_batched(sdc_context *c, int nbox, const box_desc *boxes, double *co
   if (rc) return rc;
   if (!(dt > 0) || nsteps < 1) return fail(c, SDC_EINVAL, "dt must be > 0 and nsteps >= 1");
   HIPCHECK(c, hipSetDevice(c->device));
-  Plan *pl;
-  rc = get_plan(c, nbox, boxes, U, &pl);
-  if (rc) return rc;
-  rc = run_sdc(c, pl, FRef{nullptr, pl->d_Utab}, dt, nsteps, scheme, workspace, ws_bytes,
-               (hipStream_t)stream);
-  if (rc) return rc;
+  return step_entry(c, nbox, boxes, U, dt, nsteps, scheme, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int sdc_set_graph(sdc_context *c, int enable) {
+  if (!c) return SDC_EINVAL;
+  c->use_graph = enable != 0;
+  if (!enable) {
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+  }
+  return SDC_OK;
+}
+
+int sdc_autotune(sdc_context *c, int nbox, const box_desc *boxes, double *const *U, void *workspace,
+                 size_t ws_bytes, void *stream, int *choice) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  if (nbox < 1 || !boxes || !U || !workspace) return fail(c, SDC_EINVAL, "bad batch");
+  for (int i = 0; i < nbox; ++i) {
+    int rc = check_box(c, boxes + i);
+    if (rc) return rc;
+  }
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan probe;
+  for (int i = 0; i < nbox; ++i) {
+    probe.totS += (long long)(boxes[i].nx + 8) * (boxes[i].ny + 8) * (boxes[i].nz + 8);
+    probe.totI += (long long)boxes[i].nx * boxes[i].ny * boxes[i].nz;
+  }
+  const sdc_scheme sr{2, 1, 0, 1};
+  const WsLayout L = ws_layout(&probe, c->ops->ns, &sr);
+  if (ws_bytes < L.total * sizeof(double)) return fail(c, SDC_ENOMEM, "workspace too small for tuning");
+  double *W = (double *)workspace;
+  double *P = W + L.P, *G = W + L.G, *F = W + L.F1;
+  static const TileShape cands[] = {{64, 4, 1}, {32, 8, 1}, {16, 16, 1}, {16, 8, 2}, {16, 4, 4},
+                                    {8, 8, 4}, {32, 4, 2}, {64, 2, 2}};
+  const int ncand = (int)(sizeof(cands) / sizeof(cands[0]));
+  const int caps[] = {0, 2 * std::max(c->n_cu, 1), 4 * std::max(c->n_cu, 1), 8 * std::max(c->n_cu, 1)};
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0));
+  HIPCHECK(c, hipEventCreate(&e1));
+  const TileShape fI = c->forceI, fS = c->forceS;
+  const int fcap = c->grid_cap;
+  float best = 1e30f;
+  int bi = 0, bc = 0;
+  hipStream_t st = (hipStream_t)stream;
+  std::unique_ptr<Profiler> saved = std::move(c->prof);
+  for (int ci = 0; ci < ncand; ++ci)
+    for (int k = 0; k < 4; ++k) {
+      c->forceI = cands[ci];
+      c->forceS = cands[ci];
+      c->grid_cap = caps[k];
+      Plan *pl;
+      int rc = get_plan(c, nbox, boxes, nbox > 1 ? U : nullptr, &pl);
+      if (rc) break;
+      const LaunchCtx l = make_lc(c, pl, st);
+      FRef Uref = nbox > 1 ? FRef{nullptr, pl->d_Utab} : FRef{U[0], nullptr};
+      float t = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        (void)hipEventRecord(e0, st);
+        eval_rhs_g(c->ops, l, Uref, P, G, FRef{F, nullptr}, RHS_ALL);
+        (void)hipEventRecord(e1, st);
+        HIPCHECK(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) t = std::min(t, ms);
+      }
+      if (t < best) {
+        best = t;
+        bi = ci;
+        bc = k;
+      }
+    }
+  c->prof = std::move(saved);
+  c->forceI = fI;
+  c->forceS = fS;
+  c->grid_cap = fcap;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tuned[box_signature(nbox, boxes)] = sdc_context::Tuned{cands[bi], cands[bi], caps[bc]};
+  if (choice) {
+    choice[0] = cands[bi].tx;
+    choice[1] = cands[bi].ty;
+    choice[2] = cands[bi].tz;
+    choice[3] = caps[bc];
+  }
   HIPCHECK(c, hipGetLastError());
   return SDC_OK;
 }

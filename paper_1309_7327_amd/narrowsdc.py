@@ -59,14 +59,21 @@ _SIGS = {
                          ctypes.POINTER(Scheme), _vp, ctypes.c_size_t, _vp],
     "last_status": [_vp, _vp],
     "sdc_set_tiles": [_vp, _ip, _ip, _ip, _ip, _ip, _ip, _ip],
+    "sdc_set_graph": [_vp, _ip],
+    "sdc_autotune": [_vp, _ip, ctypes.POINTER(BoxDesc), ctypes.POINTER(_vp), _vp, ctypes.c_size_t, _vp,
+                     ctypes.POINTER(ctypes.c_int)],
+    "sdc_profile_enable": [_vp, _ip],
+    "sdc_profile_read": [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)],
 }
 for _name, _args in _SIGS.items():
     getattr(_lib, _name).argtypes = _args
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.last_error_message.argtypes = [_vp]
 _lib.last_error_message.restype = ctypes.c_char_p
+_lib.sdc_kernel_name.argtypes = [_ip]
+_lib.sdc_kernel_name.restype = ctypes.c_char_p
 
-EXPORTS = list(_SIGS) + ["last_error_message"]
+EXPORTS = list(_SIGS) + ["last_error_message", "sdc_kernel_name"]
 
 
 class NarrowSDCError(RuntimeError):
@@ -175,6 +182,28 @@ class Context:
 
     def set_tiles(self, interior=(0, 0, 0), stored=(0, 0, 0), grid_cap=0):
         self._check(_lib.sdc_set_tiles(self.h, *interior, *stored, grid_cap))
+
+    def set_graph(self, enable=True):
+        self._check(_lib.sdc_set_graph(self.h, 1 if enable else 0))
+
+    def autotune(self, boxes, Us, ws, ws_bytes, stream=None):
+        arr = (BoxDesc * len(boxes))(*boxes)
+        ptrs = (ctypes.c_void_p * len(Us))(*[_ptr(u).value for u in Us])
+        ch = (ctypes.c_int * 4)()
+        self._check(_lib.sdc_autotune(self.h, len(boxes), arr, ptrs, _ptr(ws), ws_bytes, _stream(stream), ch))
+        return tuple(ch)
+
+    def profile(self, enable=True):
+        self._check(_lib.sdc_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self, stream=None):
+        """{kernel name: (total ms, launches)} since the last read."""
+        tot = (ctypes.c_double * 16)()
+        cnt = (ctypes.c_int * 16)()
+        n = _lib.sdc_profile_read(self.h, _stream(stream), tot, cnt)
+        if n < 0:
+            self._check(n)
+        return {_lib.sdc_kernel_name(i).decode(): (tot[i], cnt[i]) for i in range(n) if cnt[i] > 0}
 
 
 # ------------------------------------------------------------- helpers
