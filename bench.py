@@ -62,7 +62,7 @@ def work_model(ns, n_coarse, n_fine_per_interval):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "api.cpp", "nsdc_internal.h", "launch.h"):
+    for f in ("kernels.hip", "adjoint.hip", "physics.h", "api.cpp", "nsdc_internal.h", "launch.h"):
         with open(os.path.join(ROOT, "paper_1309_7327_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -111,6 +111,109 @@ def cpu_baseline(workload, mech, n_cells_full):
             "kind": "oracle",
             "sample": f"one step of the same scheme on a {edge}^3 box of the same recipe "
                       f"({el:.1f} s), scaled by cell count to {round(n_cells_full ** (1 / 3))}^3"}
+
+
+def bench_adjoint(args):
+    """The adjoint workload: vector-Jacobian product of the right-hand side
+    and the adjoint of 5 single-rate SDC steps on a 64^3 box, each timed
+    against its forward counterpart."""
+    import numpy as np
+    import torch
+    from paper_1309_7327_amd import narrowsdc as N
+    from synth import mechanism
+    from synth.workloads import WORKLOADS, make_primitives, time_step
+
+    wl = WORKLOADS[args.workload]
+    mech = mechanism.load(wl["mech"])
+    ns, nr = mech["ns"], mech["nr"]
+    nU = 5 + ns
+    nz, ny, nx = wl["shape"]
+    ncell = nx * ny * nz
+    dt = time_step(args.workload)
+    sd = wl["scheme"]
+    nsteps = wl["steps"]
+    sch = N.scheme(sd["n_coarse"], sd["sweeps"], 0, 1)
+    torch.cuda.set_device(0)
+    ctx = N.Context(0)
+    ctx.set_mechanism(mech)
+    prim = make_primitives(args.workload, mech)
+    bx = N.box(nx, ny, nz, wl["dx"])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    U = torch.zeros(N.ghosted_shape(nU, nz, ny, nx), dtype=torch.float64, device="cuda")
+    ctx.prim_to_cons(bx, dev(prim["p"]), dev(prim["T"]), dev(prim["Y"]), dev(prim["u"]), U)
+    g = torch.Generator(device="cuda").manual_seed(5001)
+    vbar = torch.randn((nU, nz, ny, nx), dtype=torch.float64, device="cuda", generator=g)
+    F = torch.empty_like(vbar)
+    Ub = torch.zeros_like(vbar)
+    lA = torch.zeros(nr, dtype=torch.float64, device="cuda")
+    h = torch.cuda.current_stream().cuda_stream
+    reps = max(args.steps, 1)
+
+    def timed(fn, n):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    t_rhs = timed(lambda: ctx.rhs_eval(bx, U, F, N.RHS_ALL), reps)
+    t_vjp = timed(lambda: ctx.rhs_vjp(bx, U, vbar, Ub, lA, N.RHS_ALL), reps)
+    ws, nb = N.workspace(ctx, [bx], sch)
+    U0 = U.clone()
+    t_fwd = timed(lambda: (U.copy_(U0), ctx.sdc_step(bx, U, dt, nsteps, sch, ws, nb)), 2)
+    nbv = ctx.vjp_workspace_size(bx, sch, nsteps)
+    wsv = torch.empty(nbv // 8 + 1, dtype=torch.float64, device="cuda")
+    U0b = torch.empty_like(vbar)
+    t_adj = timed(lambda: ctx.sdc_step_vjp(bx, U0, dt, nsteps, sch, vbar, U0b, lA, wsv, nbv), 2)
+    ctx.check_status()
+    # per-kernel durations of one product (HIP events on the launch stream)
+    ctx.profile(True)
+    ctx.rhs_vjp(bx, U, vbar, Ub, lA, N.RHS_ALL)
+    kern = ctx.profile_read(h)
+    ctx.profile(False)
+    ctx.check_status()
+    np_ = 8 + 3 * ns
+    # one direction adjoint launch covers a ninth of the cells; per output
+    # cell it reads the state, primitive and gradient lines and the
+    # cotangent, and updates the three adjoint accumulators
+    by_cell = 8 * (2 * nU + np_ + 4) + 16 * (nU + np_ + 4)
+    dirk = [k for k in kern if k.startswith("dir_adj")]
+    dominant = max(dirk, key=lambda k: kern[k][0])
+    dur_ms = kern[dominant][0] / kern[dominant][1]
+    ach = by_cell * ncell / 9 / (dur_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": stored_traffic(dominant, args.workload), "kernel": dominant, "avg_launch_ms": dur_ms}
+    out = {
+        "metric": "SDC adjoint steps/s (5 steps, checkpointed) and VJP time / RHS time (FP64, 1 MI355X)",
+        "value": nsteps / t_adj, "unit": "SDC adjoint steps/s", "n_gpus": 1, "steps": reps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_adj / nsteps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "cells": ncell, "species": ns, "reactions": nr, "scheme": sd,
+                   "steps": nsteps, "dt": dt},
+        "rhs_ms": 1e3 * t_rhs, "vjp_ms": 1e3 * t_vjp, "vjp_over_rhs": t_vjp / t_rhs,
+        "forward_steps_ms": 1e3 * t_fwd, "adjoint_steps_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
+        "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()}, "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import adjoint as OA
+        om = oracle.Mechanism(mech)
+        Uo = oracle.prim_to_cons(om, prim)
+        v = vbar.cpu().numpy()
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cells = np.array([[5, 6, 7], [30, 31, 32]])
+        t0 = time.perf_counter()
+        OA.rhs_vjp(om, Uo, wl["dx"], v, cells=cells, nthreads=threads)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": len(cells) / el / ncell, "unit": "rhs VJP/s", "cores": threads, "kind": "oracle",
+            "sample": f"the oracle's definition of (d rhs/dU)^T v at {len(cells)} input cells of the "
+                      f"{nx}^3 box ({el:.1f} s), scaled by cell count to one whole-box product; "
+                      f"the library: {1.0 / t_vjp:.1f} VJP/s"}
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):
@@ -227,6 +330,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if "nbox" in wl:
         return bench_batch(args)
+    if args.workload == "box64_adjoint":
+        return bench_adjoint(args)
     mech = mechanism.load(wl["mech"])
     ns = mech["ns"]
     nz, ny, nx = wl["shape"]
@@ -273,8 +378,8 @@ def main():
     t1 = time.perf_counter()
     ctx.check_status()
     import ctypes
-    tot = (ctypes.c_double * 16)()
-    cnt = (ctypes.c_int * 16)()
+    tot = (ctypes.c_double * 32)()
+    cnt = (ctypes.c_int * 32)()
     nk = lib.sdc_profile_read(ctx.h, ctypes.c_void_p(stream.cuda_stream), tot, cnt)
     lib.sdc_kernel_name.restype = ctypes.c_char_p
     lib.sdc_kernel_name.argtypes = [ctypes.c_int]

@@ -11,6 +11,8 @@
  *     eqs. (fbar), (Vc) and Section 2.4
  *   - SDC sweep: Section 3.1, eq. (expsdc); MRSDC mode 1: Section 3.2,
  *     eq. (mrupdate)
+ *   - adjoint forms: transposes of the operators above (vector-Jacobian
+ *     products of the right-hand side and of the SDC step)
  *
  * Conventions for every entry point
  *   - Fields are FP64, component-major, x fastest: field[q][z][y][x].
@@ -123,7 +125,10 @@ int sdc_workspace_size(const sdc_context *ctx, int nbox, const box_desc *boxes,
 
 /* Advance U (ghosted, in place) by nsteps steps of size dt with the scheme.
  * f(U_0) is recycled across the steps of one call.  workspace: caller-owned
- * device memory of at least sdc_workspace_size bytes; nothing is allocated. */
+ * device memory of at least sdc_workspace_size bytes holding every field
+ * array of the step.  The first call for a box (and for a multirate scheme)
+ * allocates the context's small work-list and coefficient tables; later
+ * calls with the same box and scheme allocate nothing. */
 int sdc_step(sdc_context *ctx, const box_desc *box, double *U, double dt, int nsteps,
              const sdc_scheme *scheme, void *workspace, size_t ws_bytes, void *stream);
 
@@ -152,6 +157,43 @@ int sdc_set_graph(sdc_context *ctx, int enable);
 int sdc_autotune(sdc_context *ctx, int nbox, const box_desc *boxes, double *const *U,
                  void *workspace, size_t ws_bytes, void *stream, int *choice);
 
+/* ---- adjoint forms ----------------------------------------------------
+ * Vector-Jacobian product of rhs_eval (the transpose of eq. cns as
+ * discretised in Section 2.2, stage by stage: stencils, conserved ->
+ * primitive map with the implicit-function derivative of the Newton
+ * temperature, chemistry source):
+ *   U_bar   += (d rhs / dU)^T dUdt_bar          (interior, nU components)
+ *   lnA_bar += (d rhs / d ln A_j)^T dUdt_bar     (device [nr]; may be null)
+ * U: ghosted state (device); its ghost layers are overwritten by the
+ * periodic fill, its interior is read only.  dUdt_bar: interior cotangent
+ * (device).  parts: RHS_* mask as in rhs_eval.  Uses context scratch
+ * (allocated on first use or growth).  Both outputs are accumulated, in a
+ * fixed order (no atomics): repeated calls give identical results. */
+int rhs_vjp(sdc_context *ctx, const box_desc *box, double *U, const double *dUdt_bar,
+            double *U_bar, double *lnA_bar, unsigned parts, void *stream);
+
+/* Replace ln A_j of every reaction of the current mechanism (host array
+ * [nr], synchronous).  Lets callers differentiate with respect to the
+ * pre-exponential factors at values of their choice. */
+int set_log_prefactors(sdc_context *ctx, const double *lnA);
+
+/* Bytes of device workspace sdc_step_vjp needs for nsteps steps. */
+int sdc_vjp_workspace_size(const sdc_context *ctx, const box_desc *box, const sdc_scheme *scheme,
+                           int nsteps, size_t *bytes);
+
+/* Adjoint of nsteps single-rate SDC steps (eq. expsdc; n_fine must be 0)
+ * of size dt from the state U0 (ghosted; ghost layers overwritten, interior
+ * unchanged):
+ *   U0_bar   = (d U_N / d U_0)^T UN_bar         (interior, overwritten)
+ *   lnA_bar += (d U_N / d ln A)^T UN_bar        (device [nr]; may be null)
+ * The forward steps are re-run to store the step-start states in the
+ * workspace; each step's node states are then recomputed from its
+ * checkpoint and swept backwards (one rhs_vjp per stored right-hand side).
+ * workspace: caller-owned device memory of sdc_vjp_workspace_size bytes. */
+int sdc_step_vjp(sdc_context *ctx, const box_desc *box, double *U0, double dt, int nsteps,
+                 const sdc_scheme *scheme, const double *UN_bar, double *U0_bar, double *lnA_bar,
+                 void *workspace, size_t ws_bytes, void *stream);
+
 /* Synchronise `stream`, return and clear the device error word (SDC_OK or
  * SDC_ETEMP). */
 int last_status(sdc_context *ctx, void *stream);
@@ -165,11 +207,12 @@ const char *last_error_message(const sdc_context *ctx);
  *   events recorded on its own stream.
  * sdc_profile_read: synchronise `stream`, write the summed duration (ms)
  *   and launch count of every kernel kind into total_ms[], count[] (arrays of
- *   at least 16 entries), clear the records; returns the number of kinds.
+ *   at least 32 entries), clear the records; returns the number of kinds.
  * sdc_kernel_name: name of kernel kind `id` ("" if out of range).
- * sdc_set_tiles: force the tile shapes (threads x, y, z; product <= 256) of
- *   the interior and stored index spaces (0 = automatic) and cap the number
- *   of workgroups per launch (0 = one per work item). */
+ * sdc_set_tiles: force the tile shapes (threads x, y, z; product <= 256,
+ *   interior product a multiple of 64) of the interior and stored index
+ *   spaces (0 = automatic) and cap the number of workgroups per launch
+ *   (0 = one per work item). */
 int sdc_profile_enable(sdc_context *ctx, int enable);
 int sdc_profile_read(sdc_context *ctx, void *stream, double *total_ms, int *count);
 const char *sdc_kernel_name(int id);

@@ -81,6 +81,9 @@ def lib():
         L.oracle_rhs_jvp.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_uint,
                                      dp, dp, ctypes.c_int]
+        L.oracle_rhs_jvp_cells.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_uint,
+                                           ctypes.c_int, dp, dp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -254,3 +257,19 @@ def rhs_jvp(om, U, dx, wU, wA=None, parts=ALL, nthreads=0):
     _check(lib().oracle_rhs_jvp(om.ref, nx, ny, nz, h[0], h[1], h[2], _ptr(U), _ptr(wU),
                                 _ptr(wA), parts, _ptr(out), _ptr(jvp), nthreads), "rhs_jvp")
     return out, jvp
+
+
+def rhs_jvp_cells(om, U, dx, wU, cells, wA=None, parts=ALL, nthreads=0):
+    """d rhs/dU . wU + d rhs/d lnA . wA at listed interior cells ([n][3] of
+    x, y, z) -> [n][nU]."""
+    U = _f64(U)
+    wU = _f64(wU)
+    nU, nz, ny, nx = U.shape
+    h = np.broadcast_to(np.asarray(dx, dtype=np.float64), (3,))
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    jvp = np.zeros((len(cells), nU))
+    wA = _f64(wA) if wA is not None else None
+    _check(lib().oracle_rhs_jvp_cells(om.ref, nx, ny, nz, h[0], h[1], h[2], _ptr(U), _ptr(wU),
+                                      _ptr(wA), parts, len(cells), _ptr(cells), _ptr(jvp), nthreads),
+           "rhs_jvp_cells")
+    return jvp

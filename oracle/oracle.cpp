@@ -733,4 +733,30 @@ int oracle_rhs_jvp(const omech *om, int nx, int ny, int nz, double dx, double dy
   return 0;
 }
 
+int oracle_rhs_jvp_cells(const omech *om, int nx, int ny, int nz, double dx, double dy, double dz,
+                         const double *U, const double *wU, const double *wA, unsigned parts,
+                         int ncells, const int *cells, double *jvp, int nthreads) {
+  if (nx < 1 || ny < 1 || nz < 1) return -1;
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  Mech m(om);
+  const double h[3] = {dx, dy, dz};
+  const long nin = long(nx) * ny * nz;
+  const int nU = 5 + m.ns;
+  std::vector<dual> Ud(nU * nin), dA(m.nr);
+  for (long c = 0; c < nU * nin; ++c) Ud[c] = dual(U[c], wU ? wU[c] : 0.0);
+  for (int j = 0; j < m.nr; ++j) dA[j] = dual(0.0, wA ? wA[j] : 0.0);
+  Grid<dual> g;
+  int st = setup_grid(m, nx, ny, nz, h, Ud.data(), g);
+  if (st) return st;
+#pragma omp parallel for schedule(dynamic)
+  for (int c = 0; c < ncells; ++c) {
+    int i = cells[3 * c], j = cells[3 * c + 1], k = cells[3 * c + 2];
+    std::vector<dual> o(nU);
+    rhs_cell(m, g, i, j, k, parts, o.data());
+    if (parts & ORC_REACT) react_cell(m, g, g.at(i, j, k), dA.data(), o.data());
+    for (int q = 0; q < nU; ++q) jvp[long(c) * nU + q] = o[q].d;
+  }
+  return 0;
+}
+
 }  // extern "C"

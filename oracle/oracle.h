@@ -77,6 +77,11 @@ int oracle_rhs_cells(const omech *m, int nx, int ny, int nz, double dx, double d
 int oracle_rhs_jvp(const omech *m, int nx, int ny, int nz, double dx, double dy, double dz,
                    const double *U, const double *wU, const double *wA, unsigned parts,
                    double *out, double *jvp, int nthreads);
+/* The same product evaluated only at listed interior cells (cells[3*i] = x,
+ * y, z); jvp [ncells][nU]. */
+int oracle_rhs_jvp_cells(const omech *m, int nx, int ny, int nz, double dx, double dy, double dz,
+                         const double *U, const double *wU, const double *wA, unsigned parts,
+                         int ncells, const int *cells, double *jvp, int nthreads);
 
 #ifdef __cplusplus
 }

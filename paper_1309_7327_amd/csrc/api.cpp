@@ -8,6 +8,10 @@
 // each fine node (eq. mrupdate) and piecewise-polynomial fine integration
 // matrices for fine nodes of type (b)/(c).  f(U_0) is recycled across the
 // steps of one call.
+//
+// The adjoint drivers (end of the file) run the vector-Jacobian product of
+// the right-hand side and the reverse sweep of single-rate SDC steps, with
+// step-start checkpoints and node states recomputed one step at a time.
 #include "../../include/narrowsdc.h"
 
 #include <hip/hip_runtime.h>
@@ -19,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "launch.h"
 #include "nsdc_internal.h"
 
@@ -116,10 +121,16 @@ struct Plan {
   int cap = 0;                 // workgroups per launch (0: one per work item)
   double **d_Utab = nullptr;
   std::vector<double *> Uptrs;
+  // work lists of the direction adjoint kernels (built on first use)
+  Item *d_adj = nullptr;
+  int nA[3] = {0, 0, 0};
+  size_t adj_off[3] = {0, 0, 0};
+  TileShape tsA[3]{};
   ~Plan() {
     if (d_boxes) (void)hipFree(d_boxes);
     if (d_items) (void)hipFree(d_items);
     if (d_Utab) (void)hipFree(d_Utab);
+    if (d_adj) (void)hipFree(d_adj);
   }
 };
 
@@ -187,9 +198,11 @@ void prof_end(Profiler *p, int id, hipStream_t s) {
 }
 }  // namespace nsdc
 
-static const char *KERNEL_NAMES[K_NKERNELS] = {"prim_to_cons", "ghost", "prims", "vgrad", "dir_x",
-                                               "dir_y", "dir_z", "chem", "sdc_node", "mr_fine",
-                                               "mr_src"};
+static const char *KERNEL_NAMES[K_NKERNELS] = {
+    "prim_to_cons", "ghost",     "prims",     "vgrad",     "dir_x",     "dir_y",
+    "dir_z",        "chem",      "sdc_node",  "mr_fine",   "mr_src",    "dir_adj_x",
+    "dir_adj_y",    "dir_adj_z", "chem_adj",  "vgrad_adj", "prims_adj", "fold",
+    "adj_linalg"};
 
 struct sdc_context {
   int device = 0;
@@ -995,6 +1008,7 @@ int sdc_set_tiles(sdc_context *c, int ix, int iy, int iz, int sx, int sy, int sz
   if (!c) return SDC_EINVAL;
   if (ix * iy * iz > 256 || sx * sy * sz > 256 || ix < 0 || sx < 0)
     return fail(c, SDC_EINVAL, "tile larger than 256 threads");
+  if ((ix * iy * iz) % 64 != 0) return fail(c, SDC_EINVAL, "interior tile must be a multiple of 64 threads");
   c->forceI = TileShape{ix, iy, iz};
   c->forceS = TileShape{sx, sy, sz};
   c->grid_cap = grid_cap;
@@ -1034,5 +1048,379 @@ int sdc_profile_read(sdc_context *c, void *stream, double *total_ms, int *count)
 }
 
 const char *sdc_kernel_name(int id) { return (id >= 0 && id < K_NKERNELS) ? KERNEL_NAMES[id] : ""; }
+
+}  // extern "C"
+
+// ================================================================ adjoint
+namespace {
+
+// tile shape for a (compressed) index space of extents a, b, c: 256 threads
+TileShape adj_tile(int a, int b) {
+  auto p2 = [](int v, int cap) {
+    int t = 1;
+    while (t < v && t < cap) t <<= 1;
+    return t;
+  };
+  TileShape t;
+  t.tx = p2(a, 64);
+  t.ty = p2(b, 256 / t.tx);
+  t.tz = 256 / (t.tx * t.ty);
+  return t;
+}
+
+// Work lists of the direction adjoint kernels: for direction D the interior
+// cells with the D coordinate divided by nine (rounded up).
+int adj_items(sdc_context *c, Plan *p, AdjItems &ai) {
+  if (!p->d_adj) {
+    std::vector<Item> all;
+    for (int d = 0; d < 3; ++d) {
+      int mx = 0, my = 0;
+      for (const box_desc &b : p->boxes) {
+        int n[3] = {b.nx, b.ny, b.nz};
+        n[d] = (n[d] + 8) / 9;
+        mx = std::max(mx, n[0]);
+        my = std::max(my, n[1]);
+      }
+      const TileShape ts = adj_tile(mx, my);
+      p->tsA[d] = ts;
+      p->adj_off[d] = all.size();
+      for (int bi = 0; bi < p->nbox; ++bi) {
+        const box_desc &b = p->boxes[bi];
+        int n[3] = {b.nx, b.ny, b.nz};
+        n[d] = (n[d] + 8) / 9;
+        for (int z = 0; z < n[2]; z += ts.tz)
+          for (int y = 0; y < n[1]; y += ts.ty)
+            for (int x = 0; x < n[0]; x += ts.tx) all.push_back(Item{bi, x, y, z});
+      }
+      p->nA[d] = (int)(all.size() - p->adj_off[d]);
+    }
+    HIPCHECK(c, hipMalloc(&p->d_adj, sizeof(Item) * all.size()));
+    HIPCHECK(c, hipMemcpy(p->d_adj, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice));
+  }
+  for (int d = 0; d < 3; ++d) {
+    ai.items[d] = p->d_adj + p->adj_off[d];
+    ai.n[d] = p->nA[d];
+    ai.ts[d] = p->tsA[d];
+  }
+  return SDC_OK;
+}
+
+// scratch of one vector-Jacobian product (doubles): primitive fields and
+// velocity gradient of the forward evaluation, then the adjoint
+// accumulators (contiguous, cleared together) and the ln A partials
+struct VjpLayout {
+  size_t P, G, Pb, Gb, Ub, part, total;
+};
+VjpLayout vjp_layout(const Plan *p, int ns, int nr, int cap) {
+  VjpLayout w{};
+  const int nU = 5 + ns, nP = 8 + 3 * ns;
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    size_t o = off;
+    off += (n + 31) & ~size_t(31);
+    return o;
+  };
+  w.P = take((size_t)p->totS * nP);
+  w.G = take((size_t)p->totS * 9);
+  w.Pb = take((size_t)p->totS * nP);
+  w.Gb = take((size_t)p->totS * 9);
+  w.Ub = take((size_t)p->totS * nU);
+  const int nblk = std::max(1, std::min(p->nI, cap));
+  w.part = take((size_t)nblk * std::max(nr, 1));
+  w.total = off;
+  return w;
+}
+
+int grid_cap_of(const sdc_context *c, const Plan *p) {
+  return c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : 1 << 30);
+}
+
+// Ubar (interior) += (d rhs/dU)^T V, lnA_bar += (d rhs/d ln A)^T V.
+int rhs_vjp_g(sdc_context *c, Plan *p, const LaunchCtx &l, double *U, const double *V, double *Ubar,
+              double *lnA_bar, unsigned parts, double *W) {
+  const Ops *o = c->ops;
+  const AdjOps *a = adj_ops_for(o->ns);
+  const int ns = o->ns, nU = 5 + ns;
+  const VjpLayout L = vjp_layout(p, ns, c->h_mech.nr, grid_cap_of(c, p));
+  AdjItems ai;
+  int rc = adj_items(c, p, ai);
+  if (rc) return rc;
+  double *P = W + L.P, *G = W + L.G;
+  const FRef Uf{U, nullptr};
+  o->ghost(l, Uf);
+  o->prims(l, Uf, P, FRef{nullptr, nullptr}, 0);
+  if (parts & RHS_DIFF) o->vgrad(l, P, G);
+  adj_fill0(l, W + L.Pb, (long long)(L.Ub - L.Pb) + (long long)p->totS * nU);
+  const AdjBufs ab{W + L.Ub, W + L.Pb, W + L.Gb};
+  if (parts & RHS_AD) {
+    for (int d = 0; d < 3; ++d) {
+      int nmax = 0;
+      for (const box_desc &b : p->boxes) nmax = std::max(nmax, d == 0 ? b.nx : (d == 1 ? b.ny : b.nz));
+      for (int r = 0; r < 9 && r < nmax; ++r) a->dir(l, ai, d, r, U, P, G, V, ab, parts & RHS_AD);
+    }
+  }
+  int nblk = 0;
+  if (parts & RHS_REACT) nblk = a->chem(l, U, V, ab, W + L.part);
+  if (parts & RHS_DIFF) a->vgrad(l, ab);
+  a->prims(l, U, ab);
+  a->fold(l, ab, Ubar);
+  if ((parts & RHS_REACT) && lnA_bar && c->h_mech.nr > 0) adj_lnA_reduce(l, W + L.part, nblk, c->h_mech.nr, lnA_bar);
+  return SDC_OK;
+}
+
+// workspace of the SDC adjoint (doubles): one VJP scratch, the step-start
+// checkpoints, the node states of one step, the right-hand sides of the
+// recomputation and the adjoint arrays
+struct SdcVjpLayout {
+  VjpLayout v;
+  size_t ckpt, nodes, F, A, total;
+};
+SdcVjpLayout sdc_vjp_layout(const Plan *p, int ns, int nr, int cap, const sdc_scheme *s, int nsteps) {
+  SdcVjpLayout w{};
+  w.v = vjp_layout(p, ns, nr, cap);
+  const int nU = 5 + ns, M = s->n_coarse - 1, K = s->sweeps;
+  const size_t fS = (size_t)p->totS * nU, fI = (size_t)p->totI * nU;
+  size_t off = w.v.total;
+  w.ckpt = off;
+  off += fS * nsteps;
+  w.nodes = off;
+  off += fS * (size_t)K * M;
+  w.F = off;
+  off += fI * (2 * M + 1);
+  w.A = off;
+  off += fI * (4 + 2 * (M + 1));
+  w.total = off;
+  return w;
+}
+
+int check_vjp_args(sdc_context *c, const box_desc *box) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  const TileShape t = c->forceI;
+  if (t.tx && (t.tx * t.ty * t.tz) % 64) return fail(c, SDC_EINVAL, "interior tile must be a multiple of 64 threads");
+  return SDC_OK;
+}
+
+void sdc_tables(const sdc_scheme *s, double Sm[8][8], double dtau[8]) {
+  std::vector<long double> t = gauss_lobatto(s->n_coarse);
+  const int M = s->n_coarse - 1;
+  for (int m = 0; m < M; ++m) {
+    dtau[m] = (double)(t[m + 1] - t[m]);
+    for (int j = 0; j <= M; ++j) Sm[m][j] = (double)lagrange_integral(t, j, t[m], t[m + 1]);
+  }
+}
+
+// One single-rate SDC step from X (ghosted) with every node state kept:
+// node[k M + m - 1] = U^{k+1}_m, m = 1..M (the same launches and arguments
+// as the forward driver, so the states are identical).
+void sdc_forward_record(const Ops *o, const LaunchCtx &l, double *X, double dt, const sdc_scheme *s,
+                        double *P, double *G, double *Fbase, long long fI, long long fS, double *nodes) {
+  const int M = s->n_coarse - 1, K = s->sweeps;
+  double Sm[8][8] = {}, dtau[8] = {};
+  sdc_tables(s, Sm, dtau);
+  double *F0 = Fbase;
+  double *FA[8], *FB[8];
+  for (int m = 1; m <= M; ++m) {
+    FA[m] = Fbase + fI * m;
+    FB[m] = Fbase + fI * (M + m);
+  }
+  eval_rhs_g(o, l, FRef{X, nullptr}, P, G, FRef{F0, nullptr}, RHS_ALL);
+  const double *Fold[8];
+  for (int j = 0; j <= M; ++j) Fold[j] = F0;
+  double *Fnew[8];
+  for (int k = 0; k < K; ++k) {
+    Fnew[0] = F0;
+    for (int m = 1; m <= M; ++m) Fnew[m] = (k % 2 == 0) ? FA[m] : FB[m];
+    FRef Ucur{X, nullptr};
+    for (int m = 0; m < M; ++m) {
+      if (m > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL);
+      FRef Unext{nodes + fS * ((long long)k * M + m), nullptr};
+      NodeArgs a{};
+      for (int j = 0; j <= M; ++j) {
+        a.Fold[j] = Fold[j];
+        a.S[j] = Sm[m][j];
+      }
+      a.nnodes = M + 1;
+      a.Fnew_m = Fnew[m];
+      a.Fold_m = Fold[m];
+      a.dtau = dtau[m] * dt;
+      a.dt = dt;
+      o->sdc_node(l, Ucur, Unext, a);
+      Ucur = Unext;
+    }
+    if (k < K - 1) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL);
+    for (int j = 0; j <= M; ++j) Fold[j] = Fnew[j];
+  }
+}
+
+// Reverse sweep of nsteps single-rate SDC steps.  For the update
+//   U^k_{m+1} = U^k_m + dtau_m (F^k_m - F^{k-1}_m) + dt sum_j S_mj F^{k-1}_j
+// (F^k_m = f(U^k_m) for m >= 1, F^k_0 = f(U_0), sweep 0 spreads U_0 and
+// f(U_0) to every node) the adjoint R of U^k_{m+1} gives
+//   Fb^k_m += dtau_m R,  Fb^{k-1}_j += (dt S_mj - [j = m] dtau_m) R,
+//   R(U^k_m) = R + J(U^k_m)^T Fb^k_m   (m >= 1),
+// swept from the last sweep and node back to U_0.
+int run_sdc_vjp(sdc_context *c, Plan *p, double *U0, double dt, int nsteps, const sdc_scheme *s,
+                const double *UNbar, double *U0bar, double *lnA_bar, void *ws, size_t ws_bytes, hipStream_t st) {
+  const Ops *o = c->ops;
+  const int ns = o->ns, nU = 5 + ns, M = s->n_coarse - 1, K = s->sweeps;
+  const SdcVjpLayout L = sdc_vjp_layout(p, ns, c->h_mech.nr, grid_cap_of(c, p), s, nsteps);
+  if (!ws) return fail(c, SDC_EINVAL, "null workspace");
+  if (ws_bytes < L.total * sizeof(double)) return fail(c, SDC_ENOMEM, "workspace too small");
+  double *W = (double *)ws;
+  double *P = W + L.v.P, *G = W + L.v.G;
+  const LaunchCtx l = make_lc(c, p, st);
+  const long long fI = p->totI * nU, fS = p->totS * nU;
+  double Sm[8][8] = {}, dtau[8] = {};
+  sdc_tables(s, Sm, dtau);
+  double *ckpt = W + L.ckpt, *nodes = W + L.nodes, *Fw = W + L.F;
+  double *R = W + L.A, *Rout = R + fI, *U0b = R + 2 * fI, *F0b = R + 3 * fI;
+  double *Fb = R + 4 * fI, *Fbm = Fb + fI * (M + 1);
+  auto node = [&](int k, int m) { return nodes + fS * ((long long)(k - 1) * M + (m - 1)); };
+  auto vjp = [&](double *U, const double *V, double *out) {
+    return rhs_vjp_g(c, p, l, U, V, out, lnA_bar, RHS_ALL, W);
+  };
+  // step-start checkpoints
+  HIPCHECK(c, hipMemcpyAsync(ckpt, U0, sizeof(double) * fS, hipMemcpyDeviceToDevice, st));
+  for (int n = 0; n + 1 < nsteps; ++n) {
+    sdc_forward_record(o, l, ckpt + fS * n, dt, s, P, G, Fw, fI, fS, nodes);
+    HIPCHECK(c, hipMemcpyAsync(ckpt + fS * (n + 1), node(K, M), sizeof(double) * fS, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHECK(c, hipMemcpyAsync(Rout, UNbar, sizeof(double) * fI, hipMemcpyDeviceToDevice, st));
+  for (int n = nsteps - 1; n >= 0; --n) {
+    sdc_forward_record(o, l, ckpt + fS * n, dt, s, P, G, Fw, fI, fS, nodes);
+    adj_fill0(l, U0b, 2 * fI + fI * (M + 1));   // U0b, F0b, Fb
+    double *cur = Fb, *prev = Fbm;
+    for (int k = K; k >= 1; --k) {
+      adj_fill0(l, prev, fI * (M + 1));
+      if (k == K) {
+        HIPCHECK(c, hipMemcpyAsync(R, Rout, sizeof(double) * fI, hipMemcpyDeviceToDevice, st));
+      } else {
+        adj_fill0(l, R, fI);
+        int rc = vjp(node(k, M), cur + fI * M, R);
+        if (rc) return rc;
+      }
+      for (int m = M - 1; m >= 0; --m) {
+        AxpyArgs a{};
+        a.nt = M + 2;
+        a.Y[0] = cur + fI * m;
+        a.c[0] = dtau[m] * dt;
+        for (int j = 0; j <= M; ++j) {
+          a.Y[1 + j] = prev + fI * j;
+          a.c[1 + j] = dt * Sm[m][j] - (j == m ? dtau[m] * dt : 0.0);
+        }
+        adj_axpy(l, R, a, fI);
+        if (m >= 1) {
+          int rc = vjp(node(k, m), cur + fI * m, R);
+          if (rc) return rc;
+        } else {
+          AxpyArgs u{};
+          u.nt = 1;
+          u.Y[0] = U0b;
+          u.c[0] = 1.0;
+          adj_axpy(l, R, u, fI);
+          u.Y[0] = F0b;
+          adj_axpy(l, cur, u, fI);
+        }
+      }
+      std::swap(cur, prev);
+    }
+    // sweep 0: every node value of the first sweep's "old" iterate is f(U_0)
+    LincombArgs lc{};
+    lc.nt = M + 2;
+    lc.X[0] = F0b;
+    lc.c[0] = 1.0;
+    for (int j = 0; j <= M; ++j) {
+      lc.X[1 + j] = cur + fI * j;
+      lc.c[1 + j] = 1.0;
+    }
+    adj_lincomb(l, lc, F0b, fI);
+    HIPCHECK(c, hipMemcpyAsync(Rout, U0b, sizeof(double) * fI, hipMemcpyDeviceToDevice, st));
+    int rc = vjp(ckpt + fS * n, F0b, Rout);
+    if (rc) return rc;
+  }
+  HIPCHECK(c, hipMemcpyAsync(U0bar, Rout, sizeof(double) * fI, hipMemcpyDeviceToDevice, st));
+  return SDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rhs_vjp(sdc_context *c, const box_desc *box, double *U, const double *dUdt_bar, double *U_bar,
+            double *lnA_bar, unsigned parts, void *stream) {
+  int rc = check_vjp_args(c, box);
+  if (rc) return rc;
+  if (!U || !dUdt_bar || !U_bar) return fail(c, SDC_EINVAL, "null field pointer");
+  if (parts == 0 || (parts & ~7u)) return fail(c, SDC_EINVAL, "bad parts mask");
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan *pl;
+  rc = get_plan(c, 1, box, nullptr, &pl);
+  if (rc) return rc;
+  const VjpLayout L = vjp_layout(pl, c->ops->ns, c->h_mech.nr, grid_cap_of(c, pl));
+  const size_t need = (L.total + 64) * sizeof(double);
+  if (need > c->scratch_bytes) {
+    HIPCHECK(c, hipStreamSynchronize((hipStream_t)stream));
+    if (c->scratch) (void)hipFree(c->scratch);
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    HIPCHECK(c, hipMalloc(&c->scratch, need));
+    c->scratch_bytes = need;
+  }
+  const LaunchCtx l = make_lc(c, pl, (hipStream_t)stream);
+  rc = rhs_vjp_g(c, pl, l, U, dUdt_bar, U_bar, lnA_bar, parts, c->scratch);
+  if (rc) return rc;
+  HIPCHECK(c, hipGetLastError());
+  return SDC_OK;
+}
+
+int set_log_prefactors(sdc_context *c, const double *lnA) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  if (!lnA && c->h_mech.nr > 0) return fail(c, SDC_EINVAL, "null lnA");
+  for (int j = 0; j < c->h_mech.nr; ++j) {
+    if (!std::isfinite(lnA[j])) return fail(c, SDC_EINVAL, "ln A must be finite");
+    c->h_mech.lnA[j] = lnA[j];
+  }
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, hipDeviceSynchronize());
+  HIPCHECK(c, hipMemcpy(c->d_mech, &c->h_mech, sizeof(DevMech), hipMemcpyHostToDevice));
+  return SDC_OK;
+}
+
+int sdc_vjp_workspace_size(const sdc_context *c, const box_desc *box, const sdc_scheme *scheme, int nsteps,
+                           size_t *bytes) {
+  if (!c || !bytes || nsteps < 1) return SDC_EINVAL;
+  if (!c->has_mech) return SDC_ENOMECH;
+  sdc_context *cc = const_cast<sdc_context *>(c);
+  if (check_box(cc, box) || check_scheme(cc, scheme) || scheme->n_fine != 0) return SDC_EINVAL;
+  Plan *pl;
+  if (get_plan(cc, 1, box, nullptr, &pl)) return SDC_EHIP;
+  *bytes = sdc_vjp_layout(pl, c->ops->ns, c->h_mech.nr, grid_cap_of(c, pl), scheme, nsteps).total * sizeof(double);
+  return SDC_OK;
+}
+
+int sdc_step_vjp(sdc_context *c, const box_desc *box, double *U0, double dt, int nsteps,
+                 const sdc_scheme *scheme, const double *UN_bar, double *U0_bar, double *lnA_bar,
+                 void *workspace, size_t ws_bytes, void *stream) {
+  int rc = check_vjp_args(c, box);
+  if (rc) return rc;
+  rc = check_scheme(c, scheme);
+  if (rc) return rc;
+  if (scheme->n_fine != 0) return fail(c, SDC_EINVAL, "the adjoint supports single-rate SDC (n_fine = 0)");
+  if (!U0 || !UN_bar || !U0_bar) return fail(c, SDC_EINVAL, "null field pointer");
+  if (nsteps < 1 || !(dt > 0)) return fail(c, SDC_EINVAL, "nsteps >= 1 and dt > 0 required");
+  HIPCHECK(c, hipSetDevice(c->device));
+  Plan *pl;
+  rc = get_plan(c, 1, box, nullptr, &pl);
+  if (rc) return rc;
+  rc = run_sdc_vjp(c, pl, U0, dt, nsteps, scheme, UN_bar, U0_bar, lnA_bar, workspace, ws_bytes,
+                   (hipStream_t)stream);
+  if (rc) return rc;
+  HIPCHECK(c, hipGetLastError());
+  return SDC_OK;
+}
 
 }  // extern "C"

@@ -26,130 +26,9 @@
 
 #include "nsdc_internal.h"
 
+#include "physics.h"
+
 namespace nsdc {
-
-constexpr double RU = 8.31446261815324;
-constexpr double PREF = 101325.0;
-// eighth-order centred first-derivative weights
-constexpr double C1 = 4.0 / 5.0, C2 = -1.0 / 5.0, C3 = 4.0 / 105.0, C4 = -1.0 / 280.0;
-
-template <int NS>
-struct Layout {
-  static constexpr int NU = 5 + NS;
-  // primitive fields stored per cell
-  static constexpr int PU = 0, PV = 1, PW = 2, PT = 3, PP = 4, PMU = 5, PLAM = 6, PRD = 7;
-  static constexpr int PY = 8, PX = 8 + NS, PH = 8 + 2 * NS;
-  static constexpr int NP = 8 + 3 * NS;
-};
-
-__device__ __forceinline__ double d1(const double *f, double idx) {
-  return (C1 * (f[5] - f[3]) + C2 * (f[6] - f[2]) + C3 * (f[7] - f[1]) + C4 * (f[8] - f[0])) * idx;
-}
-
-// ---------------------------------------------------------- thermodynamics
-__device__ __forceinline__ double cp_R(const DevMech *__restrict__ m, int k, double T) {
-  const double *a = m->cp[k];
-  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
-}
-__device__ __forceinline__ double h_RT(const DevMech *__restrict__ m, int k, double T, double invT) {
-  const double *a = m->hc[k];
-  return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + m->h6[k] * invT;
-}
-__device__ __forceinline__ double s_R(const DevMech *__restrict__ m, int k, double T, double lnT) {
-  const double *a = m->sc[k];
-  return m->cp[k][0] * lnT + T * (a[0] + T * (a[1] + T * (a[2] + T * a[3]))) + m->s7[k];
-}
-
-// Temperature from the specific internal energy e by Newton's method on
-// e(T) = sum_k Y_k R_k T (h_k/(R_k T) - 1), de/dT = c_v: start at T0 (1000 K
-// unless a nearby temperature is known), stop one iteration after the first
-// update below 1e-12 T (at most 50).
-template <int NS>
-__device__ int temperature(const DevMech *__restrict__ m, const double *Y, double e, double &T,
-                           double T0 = 1000.0) {
-  T = T0;
-  bool conv = false;
-  for (int it = 0; it < 50; ++it) {
-    const double invT = 1.0 / T;
-    double eT = 0.0, cv = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const double YR = Y[k] * m->Rk[k];
-      eT += YR * T * (h_RT(m, k, T, invT) - 1.0);
-      cv += YR * (cp_R(m, k, T) - 1.0);
-    }
-    const double dT = (eT - e) / cv;
-    T -= dT;
-    if (conv) return (T >= m->Tlo && T <= m->Thi) ? 0 : NSDC_ERR_TRANGE;
-    if (fabs(dT) <= 1e-12 * fabs(T)) conv = true;
-  }
-  return NSDC_ERR_NEWTON;
-}
-
-// Chemistry source rho omega_k (mass action, reversible Arrhenius reactions,
-// reverse rate from the equilibrium constant of the Gibbs energies):
-//   k_r = k_f exp(sum nu g/RT) (R T / p_ref)^{sum nu}.
-// Every reaction has two reactant and two product slots; an absent molecule
-// points at slot NS, a dummy species with concentration 1 and g = 0, so the
-// loop body has no branches.
-template <int NS>
-__device__ void production(const DevMech *__restrict__ m, double rho, double T, const double *Y,
-                           double *wdot) {
-  double c[NS + 1], g[NS + 1], w[NS + 1];
-  const double lnT = log(T), invT = 1.0 / T;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    c[k] = rho * Y[k] * m->invW[k];
-    g[k] = h_RT(m, k, T, invT) - s_R(m, k, T, lnT);
-    w[k] = 0.0;
-  }
-  c[NS] = 1.0;
-  g[NS] = 0.0;
-  w[NS] = 0.0;
-  const double lnRTp = log(RU * T / PREF);
-  const int nr = m->nr;
-#pragma unroll 2
-  for (int j = 0; j < nr; ++j) {
-    const int r0 = m->rs[j][0], r1 = m->rs[j][1], p0 = m->ps[j][0], p1 = m->ps[j][1];
-    const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
-    const double dg = (g[p0] + g[p1]) - (g[r0] + g[r1]);
-    const double kf = exp(lnkf);
-    const double kr = exp(lnkf + dg + m->dnu[j] * lnRTp);
-    const double q = kf * c[r0] * c[r1] - kr * c[p0] * c[p1];
-    w[r0] -= q;
-    w[r1] -= q;
-    w[p0] += q;
-    w[p1] += q;
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k) wdot[k] = w[k] * m->W[k];
-}
-
-// Conserved state of one cell -> density, velocity, mass fractions and
-// temperature.  Returns an error bit mask (0 = ok).
-template <int NS>
-__device__ int cell_state(const DevMech *__restrict__ m, const double *Uc, double &rho, double *u,
-                          double *Y, double &T, double T0 = 1000.0) {
-  rho = Uc[0];
-  const double ir = 1.0 / rho;
-  u[0] = Uc[1] * ir;
-  u[1] = Uc[2] * ir;
-  u[2] = Uc[3] * ir;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) Y[k] = Uc[5 + k] * ir;
-  const double e = Uc[4] * ir - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-  int err = rho > 0.0 ? 0 : NSDC_ERR_RHO;
-  err |= temperature<NS>(m, Y, e, T, T0);
-  return err;
-}
-
-__device__ __forceinline__ bool tile_cell(const Item &w, TileShape ts, int &x, int &y, int &z) {
-  const int t = threadIdx.x;
-  x = w.x0 + t % ts.tx;
-  y = w.y0 + (t / ts.tx) % ts.ty;
-  z = w.z0 + t / (ts.tx * ts.ty);
-  return true;
-}
 
 // ------------------------------------------------------------------ kernels
 template <int NS>
@@ -344,69 +223,6 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
       }
     }
   }
-}
-
-// The narrow operator at the centre of nine samples, written through the 9x9
-// face-difference matrix B: (H_{i+1/2} - H_{i-1/2}) = sum_{o,c} a_o B_oc u_c with
-// B_oc = M_{o-1,c-1} - M_{o,c} (eqs. DaDu, H).  bvec computes v = B u once per
-// field (B is banded: row o spans columns o-4..o+4); every coefficient paired
-// with that field then costs a nine-term dot product.
-//
-// For the paper's default free parameters (m47 = 3557/44100, m48 =
-// -2083/117600) B is a compile-time table, so its entries are instruction
-// constants; other parameter values read B from the mechanism tables.
-struct Mat9 {
-  double v[9][9];
-};
-constexpr Mat9 smc_face_matrix() {
-  const double a47 = 3557.0 / 44100.0, a48 = -2083.0 / 117600.0;
-  const double top[4][8] = {
-      {5.0 / 336 + a48, -83.0 / 3600 - a47 / 5 - 14 * a48 / 5, 299.0 / 50400 + 2 * a47 / 5 + 13 * a48 / 5,
-       17.0 / 12600 - a47 / 5 - 4 * a48 / 5, 1.0 / 1120, 0, 0, 0},
-      {-11.0 / 560 - 2 * a48, -31.0 / 360 + a47 + 3 * a48, 41.0 / 200 - 9 * a47 / 5 + 4 * a48 / 5,
-       -5927.0 / 50400 + 4 * a47 / 5 - 9 * a48 / 5, 17.0 / 600 - a47 / 5 - 4 * a48 / 5,
-       -503.0 / 50400 + a47 / 5 + 4 * a48 / 5, 0, 0},
-      {-1.0 / 280, 1097.0 / 5040 - 2 * a47 + 6 * a48, -1349.0 / 10080 + 3 * a47 - 12 * a48,
-       -887.0 / 5040 - a47 + 6 * a48, 3613.0 / 50400 + 4 * a47 / 5 - 9 * a48 / 5,
-       467.0 / 25200 - 3 * a47 / 5 + 18 * a48 / 5, 139.0 / 25200 - a47 / 5 - 9 * a48 / 5, 0},
-      {17.0 / 1680 + 2 * a48, -319.0 / 2520 + 2 * a47 - 8 * a48, -919.0 / 5040 - 2 * a47 + 6 * a48,
-       -445.0 / 2016, 583.0 / 720 - a47 + 6 * a48, -65.0 / 224 - 7 * a48, a47, a48},
-  };
-  double M[8][8] = {};
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 8; ++c) {
-      M[r][c] = top[r][c];
-      M[7 - r][7 - c] = -top[r][c];
-    }
-  Mat9 B = {};
-  for (int o = 0; o < 9; ++o)
-    for (int c = 0; c < 9; ++c)
-      B.v[o][c] = ((o >= 1 && c >= 1) ? M[o - 1][c - 1] : 0.0) - ((o <= 7 && c <= 7) ? M[o][c] : 0.0);
-  return B;
-}
-constexpr Mat9 SMC_B = smc_face_matrix();
-
-template <bool FIXED>
-__device__ __forceinline__ void bvec(const DevMech *__restrict__ m, const double *u, double *v) {
-#pragma unroll
-  for (int o = 0; o < 9; ++o) {
-    double acc = 0.0;
-#pragma unroll
-    for (int c = (o > 4 ? o - 4 : 0); c <= (o < 4 ? o + 4 : 8); ++c)
-      acc += (FIXED ? SMC_B.v[o][c] : m->B[o][c]) * u[c];
-    v[o] = acc;
-  }
-}
-__device__ __forceinline__ double dot9(const double *a, const double *v) {
-  double s = 0.0;
-#pragma unroll
-  for (int o = 0; o < 9; ++o) s += a[o] * v[o];
-  return s;
-}
-// first derivative of the pointwise product a*b
-__device__ __forceinline__ double d1p(const double *a, const double *b, double idx) {
-  return (C1 * (a[5] * b[5] - a[3] * b[3]) + C2 * (a[6] * b[6] - a[2] * b[2]) +
-          C3 * (a[7] * b[7] - a[1] * b[1]) + C4 * (a[8] * b[8] - a[0] * b[0])) * idx;
 }
 
 template <int NS, int D, bool FIXED>

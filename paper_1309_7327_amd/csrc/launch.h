@@ -9,7 +9,8 @@ namespace nsdc {
 // Kernel identities for the per-kernel timers.
 enum KernelId {
   K_PRIM_TO_CONS = 0, K_GHOST, K_PRIMS, K_VGRAD, K_DIR_X, K_DIR_Y, K_DIR_Z, K_CHEM, K_SDC_NODE,
-  K_MR_FINE, K_MR_SRC, K_NKERNELS
+  K_MR_FINE, K_MR_SRC, K_DIR_ADJ_X, K_DIR_ADJ_Y, K_DIR_ADJ_Z, K_CHEM_ADJ, K_VGRAD_ADJ, K_PRIMS_ADJ,
+  K_FOLD, K_ADJ_LINALG, K_NKERNELS
 };
 struct Profiler;
 // Record a HIP event on `s` before (begin) / after (end) a launch of kernel `id`

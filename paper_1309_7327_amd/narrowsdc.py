@@ -62,6 +62,12 @@ _SIGS = {
     "sdc_set_graph": [_vp, _ip],
     "sdc_autotune": [_vp, _ip, ctypes.POINTER(BoxDesc), ctypes.POINTER(_vp), _vp, ctypes.c_size_t, _vp,
                      ctypes.POINTER(ctypes.c_int)],
+    "rhs_vjp": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
+    "set_log_prefactors": [_vp, _vp],
+    "sdc_vjp_workspace_size": [_vp, ctypes.POINTER(BoxDesc), ctypes.POINTER(Scheme), _ip,
+                               ctypes.POINTER(ctypes.c_size_t)],
+    "sdc_step_vjp": [_vp, ctypes.POINTER(BoxDesc), _vp, _d, _ip, ctypes.POINTER(Scheme), _vp, _vp, _vp,
+                     _vp, ctypes.c_size_t, _vp],
     "sdc_profile_enable": [_vp, _ip],
     "sdc_profile_read": [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)],
 }
@@ -193,13 +199,33 @@ class Context:
         self._check(_lib.sdc_autotune(self.h, len(boxes), arr, ptrs, _ptr(ws), ws_bytes, _stream(stream), ch))
         return tuple(ch)
 
+    def rhs_vjp(self, bx, U, dUdt_bar, U_bar, lnA_bar=None, parts=RHS_ALL, stream=None):
+        """U_bar += (d rhs/dU)^T dUdt_bar; lnA_bar += (d rhs/d lnA)^T dUdt_bar."""
+        self._check(_lib.rhs_vjp(self.h, ctypes.byref(bx), _ptr(U), _ptr(dUdt_bar), _ptr(U_bar),
+                                 _ptr(lnA_bar), parts, _stream(stream)))
+
+    def set_log_prefactors(self, lnA):
+        a = np.ascontiguousarray(lnA, dtype=np.float64)
+        self._check(_lib.set_log_prefactors(self.h, ctypes.c_void_p(a.ctypes.data)))
+
+    def vjp_workspace_size(self, bx, sch, nsteps):
+        n = ctypes.c_size_t()
+        self._check(_lib.sdc_vjp_workspace_size(self.h, ctypes.byref(bx), ctypes.byref(sch), nsteps,
+                                                ctypes.byref(n)))
+        return n.value
+
+    def sdc_step_vjp(self, bx, U0, dt, nsteps, sch, UN_bar, U0_bar, lnA_bar, ws, ws_bytes, stream=None):
+        self._check(_lib.sdc_step_vjp(self.h, ctypes.byref(bx), _ptr(U0), dt, nsteps, ctypes.byref(sch),
+                                      _ptr(UN_bar), _ptr(U0_bar), _ptr(lnA_bar), _ptr(ws), ws_bytes,
+                                      _stream(stream)))
+
     def profile(self, enable=True):
         self._check(_lib.sdc_profile_enable(self.h, 1 if enable else 0))
 
     def profile_read(self, stream=None):
         """{kernel name: (total ms, launches)} since the last read."""
-        tot = (ctypes.c_double * 16)()
-        cnt = (ctypes.c_int * 16)()
+        tot = (ctypes.c_double * 32)()
+        cnt = (ctypes.c_int * 32)()
         n = _lib.sdc_profile_read(self.h, _stream(stream), tot, cnt)
         if n < 0:
             self._check(n)
