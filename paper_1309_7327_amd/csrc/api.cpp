@@ -115,7 +115,7 @@ struct Plan {
   int nbox = 0;
   long long totS = 0, totI = 0;
   BoxDev *d_boxes = nullptr;
-  Item *d_items = nullptr;   // interior, stored, ghost lists back to back
+  Item *d_items = nullptr;   // interior, stored, ghost, interior-y, interior-z lists back to back
   int nI = 0, nS = 0, nG = 0;
   TileShape tsI{}, tsS{};
   int cap = 0;                 // workgroups per launch (0: one per work item)
@@ -133,6 +133,27 @@ struct Plan {
     if (d_adj) (void)hipFree(d_adj);
   }
 };
+
+constexpr int NXCD = 8;   // accelerator complex dies of an MI355X
+
+// Reorder a work list for round-robin dispatch of workgroups over the XCDs
+// (workgroup b runs on XCD b mod 8) in a grid-stride loop of G workgroups:
+// in every round, the workgroups of one XCD take a contiguous run of the
+// natural order.
+std::vector<Item> xcd_order(const std::vector<Item> &nat, long long G) {
+  const long long n = (long long)nat.size();
+  std::vector<Item> out(nat.size());
+  if (G < 1) G = 1;
+  for (long long base = 0; base < n; base += G) {
+    const long long m = std::min(G, n - base);
+    const long long per = m / NXCD, rem = m % NXCD;
+    for (long long b = 0; b < m; ++b) {
+      const long long x = b % NXCD, loc = b / NXCD;
+      out[base + b] = nat[base + x * per + std::min(x, rem) + loc];
+    }
+  }
+  return out;
+}
 
 TileShape default_tile(int nx, int ny, int nz) {
   (void)ny;
@@ -293,7 +314,8 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
     tI = default_tile(mx, my, mz);
     tS = default_tile(nbox > 1 ? 16 : mx + 8, my + 8, mz + 8);
   }
-  std::string key = plan_key(nbox, bx, U, tI, tS) + "|cap" + std::to_string(cap);
+  std::string key = plan_key(nbox, bx, U, tI, tS) + "|cap" + std::to_string(cap) + "|gc" +
+                    std::to_string(c->grid_cap);
   auto it = c->plans.find(key);
   if (it != c->plans.end()) {
     *out = it->second.get();
@@ -307,7 +329,7 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
   p->tsS = tS;
   p->cap = cap;
   std::vector<BoxDev> hb(nbox);
-  std::vector<Item> iI, iS, iG;
+  std::vector<Item> iI, iS, iG, iY, iZ;
   for (int b = 0; b < nbox; ++b) {
     BoxDev &d = hb[b];
     d.nx = bx[b].nx; d.ny = bx[b].ny; d.nz = bx[b].nz;
@@ -324,6 +346,14 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
     for (int z = 0; z < d.nz; z += tI.tz)
       for (int y = 0; y < d.ny; y += tI.ty)
         for (int x = 0; x < d.nx; x += tI.tx) iI.push_back(Item{b, x, y, z});
+    // the same tiles with y, respectively z, varying fastest (the direction
+    // kernels along y and z share their stencil halos between neighbours)
+    for (int z = 0; z < d.nz; z += tI.tz)
+      for (int x = 0; x < d.nx; x += tI.tx)
+        for (int y = 0; y < d.ny; y += tI.ty) iY.push_back(Item{b, x, y, z});
+    for (int y = 0; y < d.ny; y += tI.ty)
+      for (int x = 0; x < d.nx; x += tI.tx)
+        for (int z = 0; z < d.nz; z += tI.tz) iZ.push_back(Item{b, x, y, z});
     for (int z = 0; z < d.sz; z += tS.tz)
       for (int y = 0; y < d.sy; y += tS.ty)
         for (int x = 0; x < d.sx; x += tS.tx) iS.push_back(Item{b, x, y, z});
@@ -333,10 +363,12 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
   p->nI = (int)iI.size();
   p->nS = (int)iS.size();
   p->nG = (int)iG.size();
+  const long long capE = c->grid_cap > 0 ? c->grid_cap : (cap > 0 ? cap : (1LL << 30));
   std::vector<Item> all;
-  all.insert(all.end(), iI.begin(), iI.end());
-  all.insert(all.end(), iS.begin(), iS.end());
-  all.insert(all.end(), iG.begin(), iG.end());
+  for (const std::vector<Item> *v : {&iI, &iS, &iG, &iY, &iZ}) {
+    const std::vector<Item> o = xcd_order(*v, std::min<long long>((long long)v->size(), capE));
+    all.insert(all.end(), o.begin(), o.end());
+  }
   HIPCHECK(c, hipMalloc(&p->d_boxes, sizeof(BoxDev) * nbox));
   HIPCHECK(c, hipMemcpy(p->d_boxes, hb.data(), sizeof(BoxDev) * nbox, hipMemcpyHostToDevice));
   HIPCHECK(c, hipMalloc(&p->d_items, sizeof(Item) * all.size()));
@@ -358,6 +390,9 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.itemsI = p->d_items;
   l.itemsS = p->d_items + p->nI;
   l.itemsG = p->d_items + p->nI + p->nS;
+  l.itemsD[0] = l.itemsI;
+  l.itemsD[1] = l.itemsG + p->nG;
+  l.itemsD[2] = l.itemsD[1] + p->nI;
   l.nI = p->nI;
   l.nS = p->nS;
   l.nG = p->nG;
@@ -589,6 +624,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
         }
         fp.q0_known = pi == 0;
         fp.eval_last = (pi == M - 1) && !last;
+        fp.nq = r;
         fp.dt = dt;
         o->mr_fine(l, Uin, Uout, c->d_fine + pi, fp, W + L.A, fI);
       }
@@ -1068,6 +1104,10 @@ TileShape adj_tile(int a, int b) {
   return t;
 }
 
+int grid_cap_of(const sdc_context *c, const Plan *p) {
+  return c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : 1 << 30);
+}
+
 // Work lists of the direction adjoint kernels: for direction D the interior
 // cells with the D coordinate divided by nine (rounded up).
 int adj_items(sdc_context *c, Plan *p, AdjItems &ai) {
@@ -1084,14 +1124,17 @@ int adj_items(sdc_context *c, Plan *p, AdjItems &ai) {
       const TileShape ts = adj_tile(mx, my);
       p->tsA[d] = ts;
       p->adj_off[d] = all.size();
+      std::vector<Item> nat;
       for (int bi = 0; bi < p->nbox; ++bi) {
         const box_desc &b = p->boxes[bi];
         int n[3] = {b.nx, b.ny, b.nz};
         n[d] = (n[d] + 8) / 9;
         for (int z = 0; z < n[2]; z += ts.tz)
           for (int y = 0; y < n[1]; y += ts.ty)
-            for (int x = 0; x < n[0]; x += ts.tx) all.push_back(Item{bi, x, y, z});
+            for (int x = 0; x < n[0]; x += ts.tx) nat.push_back(Item{bi, x, y, z});
       }
+      const std::vector<Item> o = xcd_order(nat, std::min<long long>((long long)nat.size(), grid_cap_of(c, p)));
+      all.insert(all.end(), o.begin(), o.end());
       p->nA[d] = (int)(all.size() - p->adj_off[d]);
     }
     HIPCHECK(c, hipMalloc(&p->d_adj, sizeof(Item) * all.size()));
@@ -1131,9 +1174,6 @@ VjpLayout vjp_layout(const Plan *p, int ns, int nr, int cap) {
   return w;
 }
 
-int grid_cap_of(const sdc_context *c, const Plan *p) {
-  return c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : 1 << 30);
-}
 
 // Ubar (interior) += (d rhs/dU)^T V, lnA_bar += (d rhs/d ln A)^T V.
 int rhs_vjp_g(sdc_context *c, Plan *p, const LaunchCtx &l, double *U, const double *V, double *Ubar,

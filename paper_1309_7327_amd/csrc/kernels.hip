@@ -225,8 +225,10 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
   }
 }
 
+// Occupancy: three workgroups per CU along x (a small spill), two along y
+// and z (whose larger spill costs more than the extra waves gain).
 template <int NS, int D, bool FIXED>
-__global__ __launch_bounds__(256, 2) void k_dir(const BoxDev *__restrict__ boxes,
+__global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
                                              TileShape ts, FRef Uref,
                                              const double *__restrict__ Pbase,
@@ -461,7 +463,7 @@ __global__ __launch_bounds__(256) void k_sdc_node(const BoxDev *__restrict__ box
 // for all fine sub-steps of the interval (a streaming pass over the node
 // values) into A[q][component], and k_mr_step then runs the sub-steps of a
 // cell in registers: Newton, chemistry, U += A[q] + dtau_q f2.
-template <int NS>
+template <int NS, int NQ>
 __global__ __launch_bounds__(256) void k_mr_src(const BoxDev *__restrict__ boxes,
                                                 const Item *__restrict__ items, int nitems,
                                                 TileShape ts, const FineCoef *__restrict__ fc,
@@ -480,7 +482,8 @@ __global__ __launch_bounds__(256) void k_mr_src(const BoxDev *__restrict__ boxes
     auto F1 = [&](int slot, int q) { return fp.F1base + (slot * fp.f1slot + o1 + q * nI); };
     auto F2 = [&](int slot, int k) { return fp.F2base + (slot * fp.f2slot + o2 + k * nI); };
     auto A = [&](int r, int q) { return Abase + (r * aslot + o1 + q * nI); };
-    const int n1 = fc->n1, nq = fc->nq, nf = fc->nfine;
+    const int n1 = fc->n1, nf = fc->nfine;
+    const int nq = NQ > 0 ? NQ : fc->nq;
     const double dt = fp.dt;
 #pragma unroll 1
     for (int q = 0; q < NU; ++q) {
@@ -488,22 +491,51 @@ __global__ __launch_bounds__(256) void k_mr_src(const BoxDev *__restrict__ boxes
 #pragma unroll
       for (int j = 0; j < 8; ++j) f1[j] = j < n1 ? F1(fp.F1old[j], q)[i] : 0.0;
       const double dF1 = F1(fp.F1new_p, q)[i] - F1(fp.F1old_p, q)[i];
-#pragma unroll 1
-      for (int r = 0; r < nq; ++r) {
-        const double dtq = fc->dtq[r] * dt;
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc += fc->S21[r][j] * f1[j];
-        double v = dtq * dF1 + dt * acc;
+      if (NQ > 0) {
+        // NQ sub-steps: the interval's NQ + 1 fine-node values of this
+        // species are loaded once, with every other operand, before any use
+        double g[NQ + 1];
         if (q >= 5) {
-          const int k = q - 5, jlo = fc->jlo[r];
-          double s22 = 0.0;
 #pragma unroll
-          for (int j = 0; j < 9; ++j)
-            if (j < nf) s22 += fc->S22[r][j] * F2(fp.F2old[jlo + j], k)[i];
-          v += dt * s22 - dtq * F2(fp.F2old[r], k)[i];
+          for (int j = 0; j <= NQ; ++j) g[j] = F2(fp.F2old[j], q - 5)[i];
         }
-        A(r, q)[i] = v;
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+          const double dtq = fc->dtq[r] * dt;
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc += fc->S21[r][j] * f1[j];
+          double v = dtq * dF1 + dt * acc;
+          if (q >= 5) {
+            const int jlo = fc->jlo[r];
+            double s22 = 0.0;
+#pragma unroll
+            for (int j = 0; j <= NQ; ++j) {
+              const int jj = j - jlo;   // position in the interpolating piece
+              if (jj >= 0 && jj < nf) s22 += fc->S22[r][jj] * g[j];
+            }
+            v += dt * s22 - dtq * g[r];
+          }
+          A(r, q)[i] = v;
+        }
+      } else {
+#pragma unroll 1
+        for (int r = 0; r < nq; ++r) {
+          const double dtq = fc->dtq[r] * dt;
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc += fc->S21[r][j] * f1[j];
+          double v = dtq * dF1 + dt * acc;
+          if (q >= 5) {
+            const int k = q - 5, jlo = fc->jlo[r];
+            double s22 = 0.0;
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+              if (j < nf) s22 += fc->S22[r][j] * F2(fp.F2old[jlo + j], k)[i];
+            v += dt * s22 - dtq * F2(fp.F2old[r], k)[i];
+          }
+          A(r, q)[i] = v;
+        }
       }
     }
   }
@@ -610,13 +642,13 @@ struct Launch {
     const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
     prof_begin(c.prof, K_DIR_X + d, c.stream);
     if (d == 0)
-      hipLaunchKernelGGL((k_dir<NS, 0, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P,
+      hipLaunchKernelGGL((k_dir<NS, 0, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nI, c.tsI, U, P,
                          G, F, parts, c.mech);
     else if (d == 1)
-      hipLaunchKernelGGL((k_dir<NS, 1, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P,
+      hipLaunchKernelGGL((k_dir<NS, 1, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nI, c.tsI, U, P,
                          G, F, parts, c.mech);
     else
-      hipLaunchKernelGGL((k_dir<NS, 2, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, U, P,
+      hipLaunchKernelGGL((k_dir<NS, 2, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nI, c.tsI, U, P,
                          G, F, parts, c.mech);
     prof_end(c.prof, K_DIR_X + d, c.stream);
   }
@@ -643,7 +675,12 @@ struct Launch {
                       const FinePtrs &fp, double *A, long long aslot) {
     const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
     prof_begin(c.prof, K_MR_SRC, c.stream);
-    hipLaunchKernelGGL(k_mr_src<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, fc, fp, A, aslot);
+    if (fp.nq == 4)
+      hipLaunchKernelGGL((k_mr_src<NS, 4>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, fc, fp, A,
+                         aslot);
+    else
+      hipLaunchKernelGGL((k_mr_src<NS, 0>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, fc, fp, A,
+                         aslot);
     prof_end(c.prof, K_MR_SRC, c.stream);
     prof_begin(c.prof, K_MR_FINE, c.stream);
     hipLaunchKernelGGL(k_mr_step<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,

@@ -20,11 +20,15 @@ void prof_end(Profiler *p, int id, hipStream_t s);
 
 // Everything a launch needs besides its field pointers: the box table, the
 // work-item lists of the three index spaces (interior tiles, stored tiles,
-// ghost-cell chunks), their tile shapes and the grid-size cap.
+// ghost-cell chunks), their tile shapes and the grid-size cap.  Lists are
+// stored in XCD order: workgroups are dispatched round-robin over the eight
+// XCDs, and the list is permuted so that the workgroups of one XCD take a
+// contiguous run of tiles in each round (neighbouring tiles share its L2).
 struct LaunchCtx {
   hipStream_t stream;
   const BoxDev *boxes;
   const Item *itemsI, *itemsS, *itemsG;
+  const Item *itemsD[3];   // the interior list ordered with direction D fastest
   int nI, nS, nG;
   TileShape tsI, tsS;
   int cap;

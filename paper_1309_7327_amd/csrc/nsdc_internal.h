@@ -16,7 +16,8 @@
 
 // Mechanism tables in device memory.  Thermodynamic polynomials are stored
 // pre-scaled for Horner evaluation of c_p/R, h/(RT) and s/R; reactions as
-// (at most) two reactant and two product species indices (-1 = none).
+// two reactant and two product species indices (ns = no molecule: a dummy
+// species of unit concentration and zero Gibbs energy).
 struct DevMech {
   int ns, nr;
   double Tlo, Thi;
@@ -98,5 +99,6 @@ struct FinePtrs {
   unsigned short F2new[NSDC_MAXFINE];   // f2 at the interval's fine nodes, iteration k+1
   int q0_known;    // f2 at the first fine node is the step-start value F2old[0]
   int eval_last;   // evaluate and store f2 at the interval's last fine node
+  int nq;          // fine sub-steps of the interval (the same as the coefficient table's)
   double dt;
 };
