@@ -128,6 +128,8 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
                                                const DevMech *__restrict__ m, int *err) {
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
+  NSDC_CHEM_LDS(NS, chem_sh);
+  double *sh = chem_sh + (chem_in_lds<NS>() ? threadIdx.x : 0);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
     for (int q = 0; q < 5; ++q) F[q * nI + i] = 0.0;
     if (out_mode == 2) {
       double wd[NS];
-      production<NS>(m, rho, T, Y, wd);
+      production_any<NS>(m, rho, T, Y, wd, sh);
 #pragma unroll
       for (int k = 0; k < NS; ++k) F[(5 + k) * nI + i] = wd[k];
     } else {
@@ -401,6 +403,8 @@ __global__ __launch_bounds__(256) void k_chem(const BoxDev *__restrict__ boxes,
                                               TileShape ts, FRef Uref, double *__restrict__ F2base,
                                               const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
+  NSDC_CHEM_LDS(NS, chem_sh);
+  double *sh = chem_sh + (chem_in_lds<NS>() ? threadIdx.x : 0);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(256) void k_chem(const BoxDev *__restrict__ boxes,
     double rho, u[3], Y[NS], T, wd[NS];
     const int e = cell_state<NS>(m, Uc, rho, u, Y, T);
     if (e) atomicOr(err, e);
-    production<NS>(m, rho, T, Y, wd);
+    production_any<NS>(m, rho, T, Y, wd, sh);
 #pragma unroll
     for (int k = 0; k < NS; ++k) F2[k * nI + i] = wd[k];
   }
@@ -487,6 +491,9 @@ __global__ __launch_bounds__(256) void k_mr_src(const BoxDev *__restrict__ boxes
     const double dt = fp.dt;
 #pragma unroll 1
     for (int q = 0; q < NU; ++q) {
+      // coefficient tables are re-read per component (scalar loads) rather
+      // than hoisted into more scalar registers than there are
+      asm volatile("" ::: "memory");
       double f1[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) f1[j] = j < n1 ? F1(fp.F1old[j], q)[i] : 0.0;
@@ -549,6 +556,8 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
                                                  const double *__restrict__ Abase, long long aslot,
                                                  const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
+  NSDC_CHEM_LDS(NS, chem_sh);
+  double *sh = chem_sh + (chem_in_lds<NS>() ? threadIdx.x : 0);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -579,7 +588,7 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
         double rho, u[3], Y[NS], T;
         errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
         Tprev = T;
-        production<NS>(m, rho, T, Y, f2);
+        production_any<NS>(m, rho, T, Y, f2, sh);
 #pragma unroll
         for (int k = 0; k < NS; ++k) F2(fp.F2new[qq], k)[i] = f2[k];
       }
@@ -590,7 +599,7 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
     if (fp.eval_last) {
       double rho, u[3], Y[NS], T, f2[NS];
       errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
-      production<NS>(m, rho, T, Y, f2);
+      production_any<NS>(m, rho, T, Y, f2, sh);
 #pragma unroll
       for (int k = 0; k < NS; ++k) F2(fp.F2new[nq], k)[i] = f2[k];
     }

@@ -51,6 +51,9 @@ __device__ int temperature(const DevMech *__restrict__ m, const double *Y, doubl
   T = T0;
   bool conv = false;
   for (int it = 0; it < 50; ++it) {
+    // keep the coefficient loads inside the iteration: hoisted, the
+    // mechanism tables exceed the scalar registers and are spilled
+    asm volatile("" ::: "memory");
     const double invT = 1.0 / T;
     double eT = 0.0, cv = 0.0;
 #pragma unroll
@@ -105,6 +108,63 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
 #pragma unroll
   for (int k = 0; k < NS; ++k) wdot[k] = w[k] * m->W[k];
 }
+
+// The same source with the per-cell arrays c, g and w in this thread's LDS
+// column: entry k of array a at sh[(a (NS+1) + k) 256] (consecutive threads
+// own consecutive doubles).  A species index then costs one address add
+// shared by the three arrays, instead of indexed register moves; every
+// operation and its order is the same as in production().
+template <int NS>
+constexpr bool chem_in_lds() {
+  return 3 * (NS + 1) * 256 * sizeof(double) <= 65536;
+}
+template <int NS>
+__device__ void production_sh(const DevMech *__restrict__ m, double rho, double T, const double *Y,
+                              double *wdot, double *sh) {
+  constexpr int S = 256, A = (NS + 1) * S;
+  const double lnT = log(T), invT = 1.0 / T;
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    sh[k * S] = rho * Y[k] * m->invW[k];
+    sh[A + k * S] = h_RT(m, k, T, invT) - s_R(m, k, T, lnT);
+    sh[2 * A + k * S] = 0.0;
+  }
+  sh[NS * S] = 1.0;
+  sh[A + NS * S] = 0.0;
+  sh[2 * A + NS * S] = 0.0;
+  const double lnRTp = log(RU * T / PREF);
+  const int nr = m->nr;
+#pragma unroll 2
+  for (int j = 0; j < nr; ++j) {
+    const int r0 = m->rs[j][0] * S, r1 = m->rs[j][1] * S, p0 = m->ps[j][0] * S, p1 = m->ps[j][1] * S;
+    const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
+    const double dg = (sh[A + p0] + sh[A + p1]) - (sh[A + r0] + sh[A + r1]);
+    const double kf = exp(lnkf);
+    const double kr = exp(lnkf + dg + m->dnu[j] * lnRTp);
+    const double q = kf * sh[r0] * sh[r1] - kr * sh[p0] * sh[p1];
+    atomicAdd(sh + 2 * A + r0, -q);
+    atomicAdd(sh + 2 * A + r1, -q);
+    atomicAdd(sh + 2 * A + p0, q);
+    atomicAdd(sh + 2 * A + p1, q);
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) wdot[k] = sh[2 * A + k * S] * m->W[k];
+}
+
+// Chemistry source through the LDS column when the block's arrays fit in
+// 64 KiB (sh: this thread's column of a [3][NS+1][256] shared array), else
+// in registers.
+template <int NS>
+__device__ __forceinline__ void production_any(const DevMech *__restrict__ m, double rho, double T,
+                                               const double *Y, double *wdot, double *sh) {
+  if constexpr (chem_in_lds<NS>())
+    production_sh<NS>(m, rho, T, Y, wdot, sh);
+  else
+    production<NS>(m, rho, T, Y, wdot);
+}
+#define NSDC_CHEM_LDS(NS, name) \
+  __shared__ double name[chem_in_lds<NS>() ? 3 * ((NS) + 1) * 256 : 1]
 
 // Conserved state of one cell -> density, velocity, mass fractions and
 // temperature.  Returns an error bit mask (0 = ok).
