@@ -17,7 +17,6 @@ events recorded on the launch stream over the timed region) and the oracle
 baseline.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -60,17 +59,10 @@ def work_model(ns, n_coarse, n_fine_per_interval):
     }
 
 
-def source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "adjoint.hip", "physics.h", "api.cpp", "nsdc_internal.h", "launch.h"):
-        with open(os.path.join(ROOT, "paper_1309_7327_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def stored_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs,
     if they were taken on the current kernel sources."""
+    from paper_1309_7327_amd.rocpd_summary import source_hash
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -328,6 +320,14 @@ def main():
     from synth.workloads import WORKLOADS, make_primitives, time_step
 
     wl = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # 1 GiB device-to-device copy: the reference for the HBM byte counters
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if "nbox" in wl:
         return bench_batch(args)
     if args.workload == "box64_adjoint":
@@ -346,13 +346,6 @@ def main():
         sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], sch_d["n_fine"], sch_d["fine_repeat"])
         r = (sch_d["n_fine"] - 1) * sch_d["fine_repeat"]
 
-    torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     ctx = N.Context(0)
     ctx.set_mechanism(mech)
     prim = make_primitives(args.workload, mech)

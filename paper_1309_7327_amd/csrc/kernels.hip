@@ -30,6 +30,12 @@
 
 namespace nsdc {
 
+// LDS bytes a workgroup of the chemistry kernels may take for the per-cell
+// species arrays (gfx950: up to 160 KiB per workgroup)
+#ifndef NSDC_CHEM_LDS_LIMIT
+#define NSDC_CHEM_LDS_LIMIT 163840
+#endif
+
 // ------------------------------------------------------------------ kernels
 template <int NS>
 __global__ __launch_bounds__(256) void k_prim_to_cons(const BoxDev *__restrict__ boxes,
@@ -128,8 +134,8 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
                                                const DevMech *__restrict__ m, int *err) {
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
-  NSDC_CHEM_LDS(NS, chem_sh);
-  double *sh = chem_sh + (chem_in_lds<NS>() ? threadIdx.x : 0);
+  NSDC_CHEM_LDS(NS, 65536, chem_sh);
+  double *sh = chem_sh + (chem_in_lds<NS, 65536>() ? threadIdx.x : 0);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
     for (int q = 0; q < 5; ++q) F[q * nI + i] = 0.0;
     if (out_mode == 2) {
       double wd[NS];
-      production_any<NS>(m, rho, T, Y, wd, sh);
+      production_any<NS, 65536>(m, rho, T, Y, wd, sh);
 #pragma unroll
       for (int k = 0; k < NS; ++k) F[(5 + k) * nI + i] = wd[k];
     } else {
@@ -403,8 +409,8 @@ __global__ __launch_bounds__(256) void k_chem(const BoxDev *__restrict__ boxes,
                                               TileShape ts, FRef Uref, double *__restrict__ F2base,
                                               const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
-  NSDC_CHEM_LDS(NS, chem_sh);
-  double *sh = chem_sh + (chem_in_lds<NS>() ? threadIdx.x : 0);
+  NSDC_CHEM_LDS(NS, NSDC_CHEM_LDS_LIMIT, chem_sh);
+  double *sh = chem_sh + (chem_in_lds<NS, NSDC_CHEM_LDS_LIMIT>() ? threadIdx.x : 0);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -422,7 +428,7 @@ __global__ __launch_bounds__(256) void k_chem(const BoxDev *__restrict__ boxes,
     double rho, u[3], Y[NS], T, wd[NS];
     const int e = cell_state<NS>(m, Uc, rho, u, Y, T);
     if (e) atomicOr(err, e);
-    production_any<NS>(m, rho, T, Y, wd, sh);
+    production_any<NS, NSDC_CHEM_LDS_LIMIT>(m, rho, T, Y, wd, sh);
 #pragma unroll
     for (int k = 0; k < NS; ++k) F2[k * nI + i] = wd[k];
   }
@@ -556,8 +562,8 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
                                                  const double *__restrict__ Abase, long long aslot,
                                                  const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
-  NSDC_CHEM_LDS(NS, chem_sh);
-  double *sh = chem_sh + (chem_in_lds<NS>() ? threadIdx.x : 0);
+  NSDC_CHEM_LDS(NS, NSDC_CHEM_LDS_LIMIT, chem_sh);
+  double *sh = chem_sh + (chem_in_lds<NS, NSDC_CHEM_LDS_LIMIT>() ? threadIdx.x : 0);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -588,7 +594,7 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
         double rho, u[3], Y[NS], T;
         errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
         Tprev = T;
-        production_any<NS>(m, rho, T, Y, f2, sh);
+        production_any<NS, NSDC_CHEM_LDS_LIMIT>(m, rho, T, Y, f2, sh);
 #pragma unroll
         for (int k = 0; k < NS; ++k) F2(fp.F2new[qq], k)[i] = f2[k];
       }
@@ -599,7 +605,7 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
     if (fp.eval_last) {
       double rho, u[3], Y[NS], T, f2[NS];
       errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
-      production_any<NS>(m, rho, T, Y, f2, sh);
+      production_any<NS, NSDC_CHEM_LDS_LIMIT>(m, rho, T, Y, f2, sh);
 #pragma unroll
       for (int k = 0; k < NS; ++k) F2(fp.F2new[nq], k)[i] = f2[k];
     }

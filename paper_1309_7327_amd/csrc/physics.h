@@ -114,9 +114,9 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
 // own consecutive doubles).  A species index then costs one address add
 // shared by the three arrays, instead of indexed register moves; every
 // operation and its order is the same as in production().
-template <int NS>
+template <int NS, int LIMIT = 65536>
 constexpr bool chem_in_lds() {
-  return 3 * (NS + 1) * 256 * sizeof(double) <= 65536;
+  return 3 * (NS + 1) * 256 * sizeof(double) <= LIMIT;
 }
 template <int NS>
 __device__ void production_sh(const DevMech *__restrict__ m, double rho, double T, const double *Y,
@@ -153,18 +153,18 @@ __device__ void production_sh(const DevMech *__restrict__ m, double rho, double 
 }
 
 // Chemistry source through the LDS column when the block's arrays fit in
-// 64 KiB (sh: this thread's column of a [3][NS+1][256] shared array), else
-// in registers.
-template <int NS>
+// LIMIT bytes (sh: this thread's column of a [3][NS+1][256] shared array),
+// else in registers.
+template <int NS, int LIMIT = 65536>
 __device__ __forceinline__ void production_any(const DevMech *__restrict__ m, double rho, double T,
                                                const double *Y, double *wdot, double *sh) {
-  if constexpr (chem_in_lds<NS>())
+  if constexpr (chem_in_lds<NS, LIMIT>())
     production_sh<NS>(m, rho, T, Y, wdot, sh);
   else
     production<NS>(m, rho, T, Y, wdot);
 }
-#define NSDC_CHEM_LDS(NS, name) \
-  __shared__ double name[chem_in_lds<NS>() ? 3 * ((NS) + 1) * 256 : 1]
+#define NSDC_CHEM_LDS(NS, LIMIT, name) \
+  __shared__ double name[chem_in_lds<NS, LIMIT>() ? 3 * ((NS) + 1) * 256 : 1]
 
 // Conserved state of one cell -> density, velocity, mass fractions and
 // temperature.  Returns an error bit mask (0 = ok).

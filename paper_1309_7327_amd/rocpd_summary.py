@@ -1,0 +1,151 @@
+"""Summaries of rocprofv3 result databases (rocpd SQLite files) as the short
+text records kept under profiles/.
+
+  python -m paper_1309_7327_amd.rocpd_summary kernels DB --title TEXT --command CMD
+      per-kernel calls / total / average duration (markdown, stdout)
+  python -m paper_1309_7327_amd.rocpd_summary traffic --fetch DB --write DB --workload NAME
+        --out-dir DIR --command-fetch CMD --command-write CMD
+      HBM bytes per launch of every library kernel from a FETCH_SIZE run and
+      a WRITE_SIZE run (KiB per dispatch), each scaled by what the same
+      counter reads for the 1 GiB device-to-device copy that
+      `bench.py --calibrate-copy` issues first; writes
+      traffic_<kernel>_<workload>.json per kernel kind and
+      traffic_<workload>.md, stamped with the hash of the kernel sources.
+"""
+import argparse
+import collections
+import hashlib
+import json
+import os
+import re
+import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ("kernels.hip", "adjoint.hip", "physics.h", "api.cpp", "nsdc_internal.h", "launch.h")
+CALIB_BYTES = 1 << 30
+
+_KINDS = [
+    (r"k_prim_to_cons<", "prim_to_cons"), (r"k_ghost<", "ghost"), (r"k_prims<", "prims"),
+    (r"k_vgrad<", "vgrad"), (r"k_dir<\d+, 0", "dir_x"), (r"k_dir<\d+, 1", "dir_y"), (r"k_dir<\d+, 2", "dir_z"),
+    (r"k_chem<", "chem"), (r"k_sdc_node<", "sdc_node"), (r"k_mr_step<", "mr_fine"), (r"k_mr_src<", "mr_src"),
+    (r"k_dir_adj<\d+, 0", "dir_adj_x"), (r"k_dir_adj<\d+, 1", "dir_adj_y"), (r"k_dir_adj<\d+, 2", "dir_adj_z"),
+    (r"k_chem_adj<", "chem_adj"), (r"k_vgrad_adj<", "vgrad_adj"), (r"k_prims_adj<", "prims_adj"),
+    (r"k_fold<", "fold"), (r"k_(fill0|axpy_multi|lincomb|lnA_reduce)\b", "adj_linalg"),
+]
+
+
+def source_hash():
+    """Hash of the kernel and driver sources (a traffic record is valid only
+    for the sources it was measured on)."""
+    h = hashlib.sha256()
+    for f in SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kind_of(name):
+    short = name.split("nsdc::")[-1]
+    for pat, kind in _KINDS:
+        if re.match(pat, short):
+            return kind
+    return None
+
+
+def short_name(name):
+    m = re.search(r"nsdc::(\w+<[^>]*>|\w+)", name)
+    return m.group(1) if m else name[:60]
+
+
+def kernel_table(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    agg = collections.OrderedDict()
+    for name, dur in rows:
+        a = agg.setdefault(short_name(name), [0, 0.0])
+        a[0] += 1
+        a[1] += dur
+    tot = sum(v[1] for v in agg.values()) or 1.0
+    return sorted(((k, n, t, t / n, 100.0 * t / tot) for k, (n, t) in agg.items()), key=lambda r: -r[2])
+
+
+def counters(db, counter):
+    """{kernel kind or short name: [values per dispatch]} for one counter."""
+    con = sqlite3.connect(db)
+    out = collections.defaultdict(list)
+    for name, cname, val in con.execute("select kernel_name, counter_name, value from counters_collection"):
+        if cname == counter:
+            out[name].append(val)
+    return out
+
+
+def traffic(fetch_db, write_db, workload, out_dir, cmd_fetch, cmd_write):
+    f = counters(fetch_db, "FETCH_SIZE")
+    w = counters(write_db, "WRITE_SIZE")
+    copy_f = max(v for k, vs in f.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in w.items() if "copyBuffer" in k for v in vs)
+    ff = CALIB_BYTES / (copy_f * 1024.0)
+    fw = CALIB_BYTES / (copy_w * 1024.0)
+    by_kind = collections.defaultdict(lambda: [[], []])
+    for k, vs in f.items():
+        if kind_of(k):
+            by_kind[kind_of(k)][0].extend(vs)
+    for k, vs in w.items():
+        if kind_of(k):
+            by_kind[kind_of(k)][1].extend(vs)
+    h = source_hash()
+    lines = [f"# HBM traffic per launch: {workload}", "",
+             "Commands (repository root on the GPU box; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```", cmd_fetch, cmd_write,
+             f"python -m paper_1309_7327_amd.rocpd_summary traffic --fetch <fetch db> --write <write db> "
+             f"--workload {workload} --out-dir profiles", "```", "",
+             f"Calibration: the 1 GiB device-to-device copy reads {copy_f:.0f} KiB (FETCH_SIZE) and writes "
+             f"{copy_w:.0f} KiB (WRITE_SIZE), so FETCH_SIZE is scaled by {ff:.3f} and WRITE_SIZE by {fw:.3f}.",
+             f"Kernel sources hash {h}.", "",
+             "| kernel | launches | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | HBM bytes per launch |",
+             "|---|---:|---:|---:|---:|"]
+    for kind in sorted(by_kind):
+        fv, wv = by_kind[kind]
+        if not fv or not wv:
+            continue
+        mf, mw = sum(fv) / len(fv), sum(wv) / len(wv)
+        b = mf * 1024.0 * ff + mw * 1024.0 * fw
+        rec = {"kernel": kind, "workload": workload, "launches": len(fv), "fetch_kib_raw": mf,
+               "write_kib_raw": mw, "fetch_factor": ff, "write_factor": fw, "bytes_per_launch": b,
+               "source_hash": h, "commands": [cmd_fetch, cmd_write]}
+        with open(os.path.join(out_dir, f"traffic_{kind}_{workload}.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        lines.append(f"| {kind} | {len(fv)} | {mf:.4g} | {mw:.4g} | {b:.4g} |")
+    with open(os.path.join(out_dir, f"traffic_{workload}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("db")
+    k.add_argument("--title", default="kernel trace")
+    k.add_argument("--command", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--out-dir", default="profiles")
+    t.add_argument("--command-fetch", default="")
+    t.add_argument("--command-write", default="")
+    a = ap.parse_args()
+    if a.cmd == "kernels":
+        print(f"# {a.title}\n")
+        if a.command:
+            print("Command (repository root on the GPU box):\n\n```\n" + a.command + "\n```\n")
+        print(f"Kernel sources hash {source_hash()}.\n")
+        print("| kernel | calls | total ns | average ns | % |\n|---|---:|---:|---:|---:|")
+        for name, n, tot, avg, pct in kernel_table(a.db):
+            print(f"| {name} | {n} | {tot:.0f} | {avg:.0f} | {pct:.2f} |")
+    else:
+        traffic(a.fetch, a.write, a.workload, a.out_dir, a.command_fetch, a.command_write)
+
+
+if __name__ == "__main__":
+    main()
