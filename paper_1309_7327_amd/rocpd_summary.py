@@ -44,17 +44,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+def short_name(name):
+    """Kernel name with its template arguments, without the parameter list."""
+    m = re.search(r"nsdc::(k_\w+(?:<[^>]*>)?)", name)
+    return m.group(1) if m else name[:60]
+
+
 def kind_of(name):
-    short = name.split("nsdc::")[-1]
+    short = short_name(name)
     for pat, kind in _KINDS:
         if re.match(pat, short):
             return kind
     return None
-
-
-def short_name(name):
-    m = re.search(r"nsdc::(\w+<[^>]*>|\w+)", name)
-    return m.group(1) if m else name[:60]
 
 
 def kernel_table(db):
