@@ -245,6 +245,10 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
   constexpr int J1 = D == 0 ? 1 : 0, J2 = D == 2 ? 1 : 2;   // the two other directions
+  // per-thread LDS column for the species centre values (up to 9 species:
+  // 36 KiB per workgroup)
+  constexpr bool SPEC_LDS = NS <= 9;
+  __shared__ double spec_sh[SPEC_LDS ? 2 * NS * 256 : 1];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -274,13 +278,17 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
     line(P + (L::PU + D) * nS, ud);
     line(P + L::PP * nS, pp);
 
+    // with the diffusive terms on, the species convective terms of the y and
+    // z passes join the species diffusion loop (more independent loads per
+    // iteration; along x the extra live registers spill)
+    constexpr bool HYP_IN_SPECIES = D != 0;
+    const bool hyp_species_apart = !HYP_IN_SPECIES || (parts & 2) == 0;
     if (parts & 1) {  // convective terms -D_D(F_D(U))
       double f[9];
-      line(U + (1 + D) * nS, f);
-      acc[0] -= d1(f, idx);
 #pragma unroll
       for (int ic = 0; ic < 3; ++ic) {
         line(U + (1 + ic) * nS, f);
+        if (ic == D) acc[0] -= d1(f, idx);
 #pragma unroll
         for (int o = 0; o < 9; ++o) f[o] = f[o] * ud[o] + (ic == D ? pp[o] : 0.0);
         acc[1 + ic] -= d1(f, idx);
@@ -289,10 +297,12 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
 #pragma unroll
       for (int o = 0; o < 9; ++o) f[o] += pp[o];
       acc[4] -= d1p(f, ud, idx);
+      if (hyp_species_apart) {
 #pragma unroll 1
-      for (int k = 0; k < NS; ++k) {
-        line(U + (5 + k) * nS, f);
-        acc[5 + k] -= d1p(f, ud, idx);
+        for (int k = 0; k < NS; ++k) {
+          line(U + (5 + k) * nS, f);
+          acc[5 + k] -= d1p(f, ud, idx);
+        }
       }
     }
 
@@ -306,7 +316,12 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
         for (int o = 0; o < 9; ++o) ke[o] = fe[o] = 0.0;
 #pragma unroll
         for (int ic = 0; ic < 3; ++ic) {
-          line(P + (L::PU + ic) * nS, u9);
+          if (ic == D) {
+#pragma unroll
+            for (int o = 0; o < 9; ++o) u9[o] = ud[o];
+          } else {
+            line(P + (L::PU + ic) * nS, u9);
+          }
           // viscous stress, second-derivative part: L_D(a, u_ic),
           // a = (4/3 mu + xi) along D, mu across
           bvec<FIXED>(m, u9, v);
@@ -359,40 +374,91 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
         const double Dpp = d1(pp, idx) / pp[4];
         const double rd4 = rd[4];
         double divVc = 0.0, Vc = 0.0;
+        if constexpr (SPEC_LDS) {
+          // one pass over the species lines: the centre values Y_k and first
+          // derivatives D_D Y_k of the final Y_k div V_c + V_c D_D Y_k terms
+          // wait in this thread's LDS column; the energy counterpart is
+          // summed over species as it goes
+          double *ysh = spec_sh + threadIdx.x;
+          double ShY = 0.0, SDhY = 0.0;
 #pragma unroll 1
-        for (int k = 0; k < NS; ++k) {
-          const double iLe = m->invLe[k];
-          line(P + (L::PX + k) * nS, u9);
-          bvec<FIXED>(m, u9, v);
-          const double DX = d1(u9, idx);
-          line(P + (L::PY + k) * nS, g);
-          const double dXY4 = u9[4] - g[4];
+          for (int k = 0; k < NS; ++k) {
+            const double iLe = m->invLe[k];
+            double y9[9];
+            if (HYP_IN_SPECIES && (parts & 1)) {
+              line(U + (5 + k) * nS, y9);
+              acc[5 + k] -= d1p(y9, ud, idx);
+            }
+            line(P + (L::PX + k) * nS, u9);
+            line(P + (L::PY + k) * nS, y9);
+            line(P + (L::PH + k) * nS, g);
+            bvec<FIXED>(m, u9, v);
+            const double DX = d1(u9, idx);
+            const double dXY4 = u9[4] - y9[4];
 #pragma unroll
-          for (int o = 0; o < 9; ++o) u9[o] -= g[o];
-          const double Lp = dot9(u9, wp);
-          const double Lx = dot9(rd, v);
-          line(P + (L::PH + k) * nS, g);
-          double LhX = 0.0, Lpe = 0.0;
+            for (int o = 0; o < 9; ++o) u9[o] -= y9[o];
+            const double Lp = dot9(u9, wp);
+            const double Lx = dot9(rd, v);
+            double LhX = 0.0, Lpe = 0.0;
 #pragma unroll
-          for (int o = 0; o < 9; ++o) {
-            LhX += rd[o] * g[o] * v[o];
-            Lpe += u9[o] * g[o] * wp[o];
+            for (int o = 0; o < 9; ++o) {
+              LhX += rd[o] * g[o] * v[o];
+              Lpe += u9[o] * g[o] * wp[o];
+            }
+            const double t = iLe * (Lx + Lp) * idx2;
+            acc[5 + k] += t;
+            divVc -= t;
+            acc[4] += iLe * (LhX + Lpe) * idx2;
+            Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
+            ysh[k * 256] = y9[4];
+            ysh[(NS + k) * 256] = d1(y9, idx);
+            ShY += g[4] * y9[4];
+            SDhY += d1p(g, y9, idx);
           }
-          const double t = iLe * (Lx + Lp) * idx2;
-          acc[5 + k] += t;
-          divVc -= t;
-          acc[4] += iLe * (LhX + Lpe) * idx2;
-          Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
-        }
-        // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart with h_k Y_k
+          // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart
+#pragma unroll
+          for (int k = 0; k < NS; ++k) acc[5 + k] += ysh[k * 256] * divVc + Vc * ysh[(NS + k) * 256];
+          acc[4] += ShY * divVc + Vc * SDhY;
+        } else {
 #pragma unroll 1
-        for (int k = 0; k < NS; ++k) {
-          line(P + (L::PY + k) * nS, u9);
-          line(P + (L::PH + k) * nS, g);
-          const double DY = d1(u9, idx);
-          const double DhY = d1p(g, u9, idx);
-          acc[5 + k] += u9[4] * divVc + Vc * DY;
-          acc[4] += g[4] * u9[4] * divVc + Vc * DhY;
+          for (int k = 0; k < NS; ++k) {
+            const double iLe = m->invLe[k];
+            if (HYP_IN_SPECIES && (parts & 1)) {
+              line(U + (5 + k) * nS, u9);
+              acc[5 + k] -= d1p(u9, ud, idx);
+            }
+            line(P + (L::PX + k) * nS, u9);
+            bvec<FIXED>(m, u9, v);
+            const double DX = d1(u9, idx);
+            line(P + (L::PY + k) * nS, g);
+            const double dXY4 = u9[4] - g[4];
+#pragma unroll
+            for (int o = 0; o < 9; ++o) u9[o] -= g[o];
+            const double Lp = dot9(u9, wp);
+            const double Lx = dot9(rd, v);
+            line(P + (L::PH + k) * nS, g);
+            double LhX = 0.0, Lpe = 0.0;
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+              LhX += rd[o] * g[o] * v[o];
+              Lpe += u9[o] * g[o] * wp[o];
+            }
+            const double t = iLe * (Lx + Lp) * idx2;
+            acc[5 + k] += t;
+            divVc -= t;
+            acc[4] += iLe * (LhX + Lpe) * idx2;
+            Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
+          }
+          // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart with h_k Y_k
+#pragma unroll 1
+          for (int k = 0; k < NS; ++k) {
+            line(P + (L::PY + k) * nS, u9);
+            line(P + (L::PH + k) * nS, g);
+            const double DY = d1(u9, idx);
+            const double DhY = d1p(g, u9, idx);
+            acc[5 + k] += u9[4] * divVc + Vc * DY;
+            acc[4] += g[4] * u9[4] * divVc + Vc * DhY;
+          }
         }
       }
     }
