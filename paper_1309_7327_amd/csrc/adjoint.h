@@ -11,14 +11,6 @@ struct AdjBufs {
   double *Ub, *Pb, *Gb;
 };
 
-// Work lists of the direction adjoint kernels: for direction D the interior
-// index space with the D extent divided by nine (cell c_D = 9 t + phase).
-struct AdjItems {
-  const Item *items[3];
-  int n[3];
-  TileShape ts[3];
-};
-
 constexpr int ADJ_MAXT = 10;
 struct AxpyArgs {
   double *Y[ADJ_MAXT];
@@ -33,8 +25,10 @@ struct LincombArgs {
 
 struct AdjOps {
   int ns;
-  void (*dir)(const LaunchCtx &, const AdjItems &, int d, int phase, const double *U, const double *P,
-              const double *G, const double *V, const AdjBufs &, unsigned parts);
+  // transpose of the direction-d terms (coef: per-cell scratch, 7 interior
+  // fields)
+  void (*dir)(const LaunchCtx &, int d, const double *U, const double *P, const double *G, const double *V,
+              const AdjBufs &, double *coef, unsigned parts);
   // returns the number of workgroups (rows of `partial`)
   int (*chem)(const LaunchCtx &, const double *U, const double *V, const AdjBufs &, double *partial);
   void (*vgrad)(const LaunchCtx &, const AdjBufs &);

@@ -3,15 +3,14 @@
 //
 // Given a cotangent vbar of dU/dt on the interior, the product
 // Ubar = (d rhs / dU)^T vbar is formed stage by stage in reverse:
-//   k_dir_adj<D>   transpose of every term that differentiates along D.  A
-//                  thread takes one output cell, re-forms the forward
-//                  quantities of its nine-point line and adds the partial
-//                  derivatives of <vbar, rhs> to the adjoints of the sampled
-//                  primitive, state and velocity-gradient fields.  Output
-//                  cells nine apart along D touch disjoint lines, so the
-//                  cells with c_D = 9 t + r (phase r) are one launch with
-//                  plain read-add-write updates: nine launches per direction,
-//                  in a fixed order, no atomics.
+//   k_adj_coef<D>  per output cell, the sums over species that the
+//                  transposed direction-D terms need (div V_c, V_c, their
+//                  adjoints, D p / p)
+//   k_adj_g1..g3   transpose of every term that differentiates along D, as a
+//                  gather: a thread takes one sample cell and collects the
+//                  contributions of the nine output cells whose lines
+//                  contain it (convective, viscous, mixed and heat terms in
+//                  g1; species diffusion and correction velocity in g2, g3)
 //   k_chem_adj     transpose of the chemistry source; also the products
 //                  with respect to ln A_j, reduced per workgroup in a fixed
 //                  order (wave butterflies, then the waves in index order)
@@ -86,30 +85,179 @@ __global__ __launch_bounds__(256) void k_lincomb(LincombArgs a, double *__restri
   }
 }
 
+// ------------------------------------------------- direction adjoint (gather)
+// For direction D, output cell i and sample o of its nine-point line, the
+// forward terms are sums over o of (per-output-cell factor) x (sample
+// value), or products with rows of B.  The adjoint of a field at a sample
+// cell s collects the contributions of the nine output cells j_o = s - (o-4)
+// e_D whose lines contain s (s is their sample o):
+//   sum_o f(j_o) dw_o                       first-derivative terms
+//   sum_o f(j_o) sum_c B_oc W[s + c - o]     the coefficient side of L (brow)
+//   sum_o f(j_o) sum_c B_co W[s + c - o]     the field side of L (bcol)
+// with W a 17-sample window of a primitive field around s.  The factors
+// that need a sum over all species of an output cell (div V_c, V_c, their
+// adjoints, D p / p) come from a per-output-cell pass (k_adj_coef).  Every
+// thread writes only its own cell: no atomics, no phases.
+
+// coefficient table per output cell and direction
+enum { CF_DIVVC = 0, CF_VC, CF_DIVVCB, CF_VCB, CF_DPP, CF_DPPB, CF_RDSELF, CF_N };
+
+namespace {
+template <bool FIXED>
+__device__ __forceinline__ double bmat(const DevMech *__restrict__ m, int o, int c) {
+  return FIXED ? SMC_B.v[o][c] : m->B[o][c];
+}
+// row o of B against the window (W[8] = the sample cell)
+template <bool FIXED>
+__device__ __forceinline__ double brow(const DevMech *__restrict__ m, const double *W, int o) {
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < 9; ++c)
+    if (c >= o - 4 && c <= o + 4) acc += bmat<FIXED>(m, o, c) * W[c - o + 8];
+  return acc;
+}
+// column o of B against the window
+template <bool FIXED>
+__device__ __forceinline__ double bcol(const DevMech *__restrict__ m, const double *W, int o) {
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < 9; ++c)
+    if (c >= o - 4 && c <= o + 4) acc += bmat<FIXED>(m, c, o) * W[c - o + 8];
+  return acc;
+}
+
+// Geometry of a gather thread: stored cell s whose two transverse
+// coordinates are interior; output cell j_o has interior D-coordinate
+// cd - o (cd = stored D-coordinate of s).  Per-lane indices are 32-bit
+// (a box has < 2^28 stored cells); field bases stay 64-bit and uniform.
+template <int D>
+struct Gather {
+  long long nS, nI;
+  int s, st, ibase, sI, cd, nD, lo, hi;
+  bool ok;
+  __device__ Gather(const BoxDev &b, int x, int y, int z) {
+    const int c[3] = {x, y, z}, n[3] = {b.nx, b.ny, b.nz};
+    ok = x < b.sx && y < b.sy && z < b.sz;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (d != D && (c[d] < NSDC_NG || c[d] >= n[d] + NSDC_NG)) ok = false;
+    nS = (long long)b.sx * b.sy * b.sz;
+    nI = (long long)b.nx * b.ny * b.nz;
+    s = (z * b.sy + y) * b.sx + x;
+    st = D == 0 ? 1 : (D == 1 ? b.sx : b.sx * b.sy);
+    sI = D == 0 ? 1 : (D == 1 ? b.nx : b.nx * b.ny);
+    cd = c[D];
+    nD = n[D];
+    const int xi = D == 0 ? 0 : x - NSDC_NG, yi = D == 1 ? 0 : y - NSDC_NG, zi = D == 2 ? 0 : z - NSDC_NG;
+    ibase = (zi * b.ny + yi) * b.nx + xi;
+    lo = s - cd * st;                              // stored D-coordinate 0
+    hi = s + (nD + 2 * NSDC_NG - 1 - cd) * st;     // last stored D-coordinate
+  }
+  __device__ bool valid(int o) const { return cd - o >= 0 && cd - o < nD; }
+  __device__ int j(int o) const { return ibase + (cd - o) * sI; }
+  // interior field value at output cell j_o (0 where j_o is not a cell)
+  __device__ double at(const double *f, int o) const { return valid(o) ? f[j(o)] : 0.0; }
+  // 17-sample window of a stored field around s (clamped at the array ends;
+  // clamped samples only meet the zero factors of absent output cells)
+  __device__ void window(const double *f, double *W) const {
+    int p = s - 8 * st;
+#pragma unroll
+    for (int mm = 0; mm < 17; ++mm, p += st) W[mm] = f[min(max(p, lo), hi)];
+  }
+};
+}  // namespace
+
+// Per output cell: the forward sums div V_c, V_c, their adjoints and the
+// pressure-gradient factor of direction D (CF_* table, interior layout).
 template <int NS, int D, bool FIXED>
-__global__ __launch_bounds__(256) void k_dir_adj(const BoxDev *__restrict__ boxes,
-                                                 const Item *__restrict__ items, int nitems,
-                                                 TileShape ts, int phase,
-                                                 const double *__restrict__ Ubase,
-                                                 const double *__restrict__ Pbase,
-                                                 const double *__restrict__ Gbase,
-                                                 const double *__restrict__ Vbase, AdjBufs ab,
-                                                 unsigned parts, const DevMech *__restrict__ m) {
+__global__ __launch_bounds__(256) void k_adj_coef(const BoxDev *__restrict__ boxes,
+                                                  const Item *__restrict__ items, int nitems, TileShape ts,
+                                                  const double *__restrict__ Pbase,
+                                                  const double *__restrict__ Vbase, double *__restrict__ coef,
+                                                  const DevMech *__restrict__ m) {
+  using L = Layout<NS>;
+  constexpr int NU = L::NU, NP = L::NP;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+    const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+    const long long i = ((long long)z * b.ny + y) * b.nx + x;
+    const long long st = D == 0 ? 1 : (D == 1 ? (long long)b.sx : (long long)b.sx * b.sy);
+    const double *P = Pbase + b.offS * NP;
+    const double *V = Vbase + b.offI * NU;
+    double *C = coef + b.offI * CF_N;
+    const double idx = b.idx[D], idx2 = b.idx2[D];
+    auto line = [&](const double *f, double *v) {
+#pragma unroll
+      for (int o = 0; o < 9; ++o) v[o] = f[s + (o - 4) * st];
+    };
+    double rd[9], pp[9], Bp[9], wp[9];
+    line(P + L::PRD * nS, rd);
+    line(P + L::PP * nS, pp);
+    bvec<FIXED>(m, pp, Bp);
+#pragma unroll
+    for (int o = 0; o < 9; ++o) wp[o] = rd[o] * Bp[o] / pp[o];
+    const double Dpp = d1(pp, idx) / pp[4];
+    const double rd4 = rd[4];
+    const double vb4 = V[4 * nI + i];
+    double divVc = 0.0, Vc = 0.0, divVcb = 0.0, Vcb = 0.0, S1 = 0.0, S2 = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < NS; ++k) {
+      const double iLe = m->invLe[k];
+      const double vbk = V[(5 + k) * nI + i];
+      double X9[9], Y9[9], h9[9], v[9];
+      line(P + (L::PX + k) * nS, X9);
+      line(P + (L::PY + k) * nS, Y9);
+      line(P + (L::PH + k) * nS, h9);
+      bvec<FIXED>(m, X9, v);
+      double Lxp = 0.0;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) Lxp += rd[o] * v[o] + (X9[o] - Y9[o]) * wp[o];
+      divVc -= iLe * Lxp * idx2;
+      const double dXY4 = X9[4] - Y9[4];
+      const double sv = iLe * (d1(X9, idx) + dXY4 * Dpp);
+      Vc -= rd4 * sv;
+      S1 += sv;
+      S2 += iLe * dXY4;
+      divVcb += (vbk + vb4 * h9[4]) * Y9[4];
+      Vcb += vbk * d1(Y9, idx) + vb4 * d1p(h9, Y9, idx);
+    }
+    C[CF_DIVVC * nI + i] = divVc;
+    C[CF_VC * nI + i] = Vc;
+    C[CF_DIVVCB * nI + i] = divVcb;
+    C[CF_VCB * nI + i] = Vcb;
+    C[CF_DPP * nI + i] = Dpp;
+    C[CF_DPPB * nI + i] = -Vcb * rd4 * S2;
+    C[CF_RDSELF * nI + i] = -Vcb * S1;
+  }
+}
+
+// Gather of the convective, viscous, mixed and heat-conduction terms of
+// direction D into the state, velocity, pressure, viscosity, conductivity,
+// temperature and velocity-gradient adjoints at sample cell s.
+template <int NS, int D, bool FIXED>
+__global__ __launch_bounds__(256) void k_adj_g1(const BoxDev *__restrict__ boxes,
+                                                const Item *__restrict__ items, int nitems, TileShape ts,
+                                                const double *__restrict__ Ubase,
+                                                const double *__restrict__ Pbase,
+                                                const double *__restrict__ Gbase,
+                                                const double *__restrict__ Vbase, AdjBufs ab, unsigned parts,
+                                                const DevMech *__restrict__ m) {
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
   constexpr int J1 = D == 0 ? 1 : 0, J2 = D == 2 ? 1 : 2;   // the two other directions
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
-    int c[3];
-    tile_cell(w, ts, c[0], c[1], c[2]);
-    c[D] = 9 * c[D] + phase;
-    if (c[0] >= b.nx || c[1] >= b.ny || c[2] >= b.nz) continue;
-    const long long nS = (long long)b.sx * b.sy * b.sz;
-    const long long nI = (long long)b.nx * b.ny * b.nz;
-    const long long s = ((long long)(c[2] + NSDC_NG) * b.sy + (c[1] + NSDC_NG)) * b.sx + (c[0] + NSDC_NG);
-    const long long i = ((long long)c[2] * b.ny + c[1]) * b.nx + c[0];
-    const long long st = D == 0 ? 1 : (D == 1 ? (long long)b.sx : (long long)b.sx * b.sy);
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    const Gather<D> g(b, x, y, z);
+    if (!g.ok) continue;
+    const long long nS = g.nS, nI = g.nI, s = g.s;
     const double *U = Ubase + b.offS * NU;
     const double *P = Pbase + b.offS * NP;
     const double *G = Gbase + b.offS * 9;
@@ -118,69 +266,48 @@ __global__ __launch_bounds__(256) void k_dir_adj(const BoxDev *__restrict__ boxe
     double *Pb = ab.Pb + b.offS * NP;
     double *Gb = ab.Gb + b.offS * 9;
     const double idx = b.idx[D], idx2 = b.idx2[D];
-    auto line = [&](const double *f, double *v) {
-#pragma unroll
-      for (int o = 0; o < 9; ++o) v[o] = f[s + (o - 4) * st];
-    };
-    auto scat = [&](double *f, const double *v) {
-#pragma unroll
-      for (int o = 0; o < 9; ++o) f[s + (o - 4) * st] += v[o];
-    };
-    double vb[NU];
-#pragma unroll
-    for (int q = 0; q < NU; ++q) vb[q] = V[q * nI + i];
     double dw[9];
     d1w(idx, dw);
-    double uu[3][9], pp[9];
+    // cotangents of momentum and energy at the nine output cells
+    double va[4][9];
 #pragma unroll
-    for (int ic = 0; ic < 3; ++ic) line(P + (L::PU + ic) * nS, uu[ic]);
-    line(P + L::PP * nS, pp);
-    // adjoints of the velocity and pressure samples, scattered at the end
-    double ub[3][9], pb[9];
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int o = 0; o < 9; ++o) {
-      ub[0][o] = ub[1][o] = ub[2][o] = 0.0;
-      pb[o] = 0.0;
+      for (int o = 0; o < 9; ++o) va[q][o] = g.at(V + (1 + q) * nI, o);
+    double T[5];   // T_q = sum_o vbar_q(j_o) dw_o
+    T[0] = 0.0;
+#pragma unroll
+    for (int o = 0; o < 9; ++o) T[0] += g.at(V, o) * dw[o];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T[1 + q] = 0.0;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) T[1 + q] += va[q][o] * dw[o];
     }
+    double us[3];
+#pragma unroll
+    for (int ic = 0; ic < 3; ++ic) us[ic] = P[(L::PU + ic) * nS + s];
+    const double ud = us[D], ps = P[L::PP * nS + s];
+    double ub[3] = {0.0, 0.0, 0.0}, pb = 0.0;
 
     if (parts & 1) {  // -D_D(F_D(U))
-      double f[9], t[9];
-#pragma unroll
-      for (int o = 0; o < 9; ++o) t[o] = -vb[0] * dw[o];
-      scat(Ub + (1 + D) * nS, t);
+      Ub[(1 + D) * nS + s] -= T[0];
 #pragma unroll
       for (int ic = 0; ic < 3; ++ic) {
-        line(U + (1 + ic) * nS, f);
-        const double a = -vb[1 + ic];
-#pragma unroll
-        for (int o = 0; o < 9; ++o) {
-          const double ao = a * dw[o];
-          t[o] = ao * uu[D][o];
-          ub[D][o] += ao * f[o];
-          if (ic == D) pb[o] += ao;
-        }
-        scat(Ub + (1 + ic) * nS, t);
+        Ub[(1 + ic) * nS + s] -= T[1 + ic] * ud;
+        ub[D] -= T[1 + ic] * U[(1 + ic) * nS + s];
+        if (ic == D) pb -= T[1 + D];
       }
-      line(U + 4 * nS, f);
-#pragma unroll
-      for (int o = 0; o < 9; ++o) {
-        const double ao = -vb[4] * dw[o];
-        t[o] = ao * uu[D][o];
-        pb[o] += ao * uu[D][o];
-        ub[D][o] += ao * (f[o] + pp[o]);
-      }
-      scat(Ub + 4 * nS, t);
+      Ub[4 * nS + s] -= T[4] * ud;
+      pb -= T[4] * ud;
+      ub[D] -= T[4] * (U[4 * nS + s] + ps);
 #pragma unroll 1
       for (int k = 0; k < NS; ++k) {
-        line(U + (5 + k) * nS, f);
-        const double a = -vb[5 + k];
+        double Tk = 0.0;
 #pragma unroll
-        for (int o = 0; o < 9; ++o) {
-          const double ao = a * dw[o];
-          t[o] = ao * uu[D][o];
-          ub[D][o] += ao * f[o];
-        }
-        scat(Ub + (5 + k) * nS, t);
+        for (int o = 0; o < 9; ++o) Tk += g.at(V + (5 + k) * nI, o) * dw[o];
+        Ub[(5 + k) * nS + s] -= Tk * ud;
+        ub[D] -= Tk * U[(5 + k) * nS + s];
       }
     }
 
@@ -188,162 +315,256 @@ __global__ __launch_bounds__(256) void k_dir_adj(const BoxDev *__restrict__ boxe
       const double bulk = m->bulk;
       const double lam2 = bulk - 2.0 / 3.0;
       const double ewD = 1.0 / 3.0 + bulk;
-      double mu[9], mub[9], v[9], bt[9], t[9];
-      line(P + L::PMU * nS, mu);
-      // every L_D(mu, .) term at once: sum_ic vb_ic c_ic L(mu, u_ic) +
-      // vb_E [(1/3 + xi) L(mu, u_D^2/2) + L(mu, |u|^2/2)]
+      double mub = 0.0, W[17], keW[17];
+      // viscous stress L_D(mu, u_ic), viscous work L_D(mu/3 + xi, u_D^2/2)
+      // and L_D(mu, |u|^2/2): field side at s ...
+      g.window(P + L::PMU * nS, W);
+      const double mus = W[8];
 #pragma unroll
       for (int o = 0; o < 9; ++o) {
-        double phi = vb[4] * (ewD * 0.5 * uu[D][o] * uu[D][o] +
-                              0.5 * (uu[0][o] * uu[0][o] + uu[1][o] * uu[1][o] + uu[2][o] * uu[2][o]));
+        const double beta = idx2 * bcol<FIXED>(m, W, o);
 #pragma unroll
-        for (int ic = 0; ic < 3; ++ic) phi += vb[1 + ic] * (ic == D ? 4.0 / 3.0 + bulk : 1.0) * uu[ic][o];
-        t[o] = phi;
+        for (int ic = 0; ic < 3; ++ic)
+          ub[ic] += beta * (va[ic][o] * (ic == D ? 4.0 / 3.0 + bulk : 1.0) +
+                            va[3][o] * (ic == D ? 1.0 + ewD : 1.0) * us[ic]);
       }
-      bvec<FIXED>(m, t, v);
+      // ... and coefficient side at s
 #pragma unroll
-      for (int o = 0; o < 9; ++o) mub[o] = idx2 * v[o];
-      btvec<FIXED>(m, mu, bt);
+      for (int mm = 0; mm < 17; ++mm) keW[mm] = 0.0;
 #pragma unroll
       for (int ic = 0; ic < 3; ++ic) {
-        const double cic = vb[1 + ic] * (ic == D ? 4.0 / 3.0 + bulk : 1.0);
-        const double ce = vb[4] * (ic == D ? 1.0 + ewD : 1.0);
+        g.window(P + (L::PU + ic) * nS, W);
 #pragma unroll
-        for (int o = 0; o < 9; ++o) ub[ic][o] += idx2 * bt[o] * (cic + ce * uu[ic][o]);
+        for (int o = 0; o < 9; ++o)
+          mub += idx2 * va[ic][o] * (ic == D ? 4.0 / 3.0 + bulk : 1.0) * brow<FIXED>(m, W, o);
+#pragma unroll
+        for (int mm = 0; mm < 17; ++mm) {
+          W[mm] = 0.5 * W[mm] * W[mm];
+          keW[mm] += W[mm];
+        }
+        if (ic == D) {
+#pragma unroll
+          for (int o = 0; o < 9; ++o) mub += idx2 * va[3][o] * ewD * brow<FIXED>(m, W, o);
+        }
       }
-      // D_D((xi - 2/3 mu) sum_{j != D} D_j u_j) and its viscous work
+#pragma unroll
+      for (int o = 0; o < 9; ++o) mub += idx2 * va[3][o] * brow<FIXED>(m, keW, o);
+      // mixed terms D_D((xi - 2/3 mu) sum_{j != D} D_j u_j), D_D(mu D_ic u_D)
+      // and their viscous work
       {
-        double g1[9], g2[9];
-        line(G + (3 * J1 + J1) * nS, g1);
-        line(G + (3 * J2 + J2) * nS, g2);
+        const double gs = G[(3 * J1 + J1) * nS + s] + G[(3 * J2 + J2) * nS + s];
+        const double Gm = T[1 + D] + us[D] * T[4];
+        mub += lam2 * gs * Gm;
+        Gb[(3 * J1 + J1) * nS + s] += lam2 * mus * Gm;
+        Gb[(3 * J2 + J2) * nS + s] += lam2 * mus * Gm;
+        ub[D] += lam2 * mus * gs * T[4];
 #pragma unroll
-        for (int o = 0; o < 9; ++o) {
-          const double gs = g1[o] + g2[o];
-          const double gbar = dw[o] * (vb[1 + D] + vb[4] * uu[D][o]);
-          ub[D][o] += vb[4] * dw[o] * lam2 * mu[o] * gs;
-          mub[o] += gbar * lam2 * gs;
-          t[o] = gbar * lam2 * mu[o];
+        for (int e = 0; e < 2; ++e) {
+          const int ic = e == 0 ? J1 : J2;
+          const double gg = G[(3 * ic + D) * nS + s];
+          const double Gi = T[1 + ic] + us[ic] * T[4];
+          mub += gg * Gi;
+          Gb[(3 * ic + D) * nS + s] += mus * Gi;
+          ub[ic] += mus * gg * T[4];
         }
-        scat(Gb + (3 * J1 + J1) * nS, t);
-        scat(Gb + (3 * J2 + J2) * nS, t);
       }
-      // D_D(mu D_ic u_D), ic != D, and its viscous work
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int ic = e == 0 ? J1 : J2;
-        double gg[9];
-        line(G + (3 * ic + D) * nS, gg);
-#pragma unroll
-        for (int o = 0; o < 9; ++o) {
-          const double gbar = dw[o] * (vb[1 + ic] + vb[4] * uu[ic][o]);
-          ub[ic][o] += vb[4] * dw[o] * mu[o] * gg[o];
-          mub[o] += gbar * gg[o];
-          t[o] = gbar * mu[o];
-        }
-        scat(Gb + (3 * ic + D) * nS, t);
-      }
-      scat(Pb + L::PMU * nS, mub);
+      Pb[L::PMU * nS + s] += mub;
       // heat conduction L_D(lambda, T)
       {
-        double T9[9], lam[9];
-        line(P + L::PT * nS, T9);
-        line(P + L::PLAM * nS, lam);
-        bvec<FIXED>(m, T9, v);
+        double lb = 0.0, tb = 0.0;
+        g.window(P + L::PT * nS, W);
 #pragma unroll
-        for (int o = 0; o < 9; ++o) t[o] = vb[4] * idx2 * v[o];
-        scat(Pb + L::PLAM * nS, t);
-        btvec<FIXED>(m, lam, bt);
+        for (int o = 0; o < 9; ++o) lb += va[3][o] * brow<FIXED>(m, W, o);
+        g.window(P + L::PLAM * nS, W);
 #pragma unroll
-        for (int o = 0; o < 9; ++o) t[o] = vb[4] * idx2 * bt[o];
-        scat(Pb + L::PT * nS, t);
-      }
-      // species diffusion and the correction velocity
-      {
-        double rd[9], rdb[9], Bp[9], wp[9], wpb[9];
-        line(P + L::PRD * nS, rd);
-        bvec<FIXED>(m, pp, Bp);
-#pragma unroll
-        for (int o = 0; o < 9; ++o) {
-          wp[o] = rd[o] * Bp[o] / pp[o];
-          rdb[o] = 0.0;
-          wpb[o] = 0.0;
-        }
-        const double Dpp = d1(pp, idx) / pp[4];
-        const double rd4 = rd[4];
-        // forward values divVc, Vc and the adjoints of both
-        double divVc = 0.0, Vc = 0.0, divVcb = 0.0, Vcb = 0.0, S1 = 0.0, S2 = 0.0;
-#pragma unroll 1
-        for (int k = 0; k < NS; ++k) {
-          const double iLe = m->invLe[k];
-          double X9[9], Y9[9], h9[9];
-          line(P + (L::PX + k) * nS, X9);
-          line(P + (L::PY + k) * nS, Y9);
-          line(P + (L::PH + k) * nS, h9);
-          bvec<FIXED>(m, X9, v);
-          double Lxp = 0.0;
-#pragma unroll
-          for (int o = 0; o < 9; ++o) Lxp += rd[o] * v[o] + (X9[o] - Y9[o]) * wp[o];
-          divVc -= iLe * Lxp * idx2;
-          const double dXY4 = X9[4] - Y9[4];
-          const double sv = iLe * (d1(X9, idx) + dXY4 * Dpp);
-          Vc -= rd4 * sv;
-          S1 += sv;
-          S2 += iLe * dXY4;
-          divVcb += (vb[5 + k] + vb[4] * h9[4]) * Y9[4];
-          Vcb += vb[5 + k] * d1(Y9, idx) + vb[4] * d1p(h9, Y9, idx);
-        }
-        rdb[4] -= Vcb * S1;
-        const double Dppb = -Vcb * rd4 * S2;
-#pragma unroll 1
-        for (int k = 0; k < NS; ++k) {
-          const double iLe = m->invLe[k];
-          double X9[9], Y9[9], h9[9], Xb[9], Yb[9], hb[9];
-          line(P + (L::PX + k) * nS, X9);
-          line(P + (L::PY + k) * nS, Y9);
-          line(P + (L::PH + k) * nS, h9);
-          bvec<FIXED>(m, X9, v);
-          const double Lxb = (vb[5 + k] - divVcb) * iLe * idx2;
-          const double Lhb = vb[4] * iLe * idx2;
-          const double cv = Vcb * rd4 * iLe;
-#pragma unroll
-          for (int o = 0; o < 9; ++o) {
-            const double e = Lxb + Lhb * h9[o];
-            const double d = X9[o] - Y9[o];
-            const double db = e * wp[o];
-            t[o] = rd[o] * e;
-            Xb[o] = -cv * dw[o] + db;
-            Yb[o] = Vc * dw[o] * (vb[5 + k] + vb[4] * h9[o]) - db;
-            hb[o] = vb[4] * Vc * dw[o] * Y9[o] + Lhb * (rd[o] * v[o] + d * wp[o]);
-            rdb[o] += v[o] * e;
-            wpb[o] += e * d;
-          }
-          Xb[4] -= cv * Dpp;
-          Yb[4] += (vb[5 + k] + vb[4] * h9[4]) * divVc + cv * Dpp;
-          hb[4] += vb[4] * Y9[4] * divVc;
-          btvec<FIXED>(m, t, bt);
-#pragma unroll
-          for (int o = 0; o < 9; ++o) Xb[o] += bt[o];
-          scat(Pb + (L::PX + k) * nS, Xb);
-          scat(Pb + (L::PY + k) * nS, Yb);
-          scat(Pb + (L::PH + k) * nS, hb);
-        }
-        // wp = rd (B p) / p and Dpp = D p / p_centre
-#pragma unroll
-        for (int o = 0; o < 9; ++o) {
-          rdb[o] += wpb[o] * Bp[o] / pp[o];
-          t[o] = wpb[o] * rd[o] / pp[o];
-          pb[o] += Dppb * dw[o] / pp[4] - wpb[o] * wp[o] / pp[o];
-        }
-        pb[4] -= Dppb * Dpp / pp[4];
-        btvec<FIXED>(m, t, bt);
-#pragma unroll
-        for (int o = 0; o < 9; ++o) pb[o] += bt[o];
-        scat(Pb + L::PRD * nS, rdb);
+        for (int o = 0; o < 9; ++o) tb += va[3][o] * bcol<FIXED>(m, W, o);
+        Pb[L::PLAM * nS + s] += idx2 * lb;
+        Pb[L::PT * nS + s] += idx2 * tb;
       }
     }
 #pragma unroll
-    for (int ic = 0; ic < 3; ++ic) scat(Pb + (L::PU + ic) * nS, ub[ic]);
-    scat(Pb + L::PP * nS, pb);
+    for (int ic = 0; ic < 3; ++ic) Pb[(L::PU + ic) * nS + s] += ub[ic];
+    Pb[L::PP * nS + s] += pb;
+  }
+}
+
+// Gather of the species diffusion and correction-velocity terms of
+// direction D, in two kernels that each carry half of the state: g2 into
+// the X_k, Y_k, h_k adjoints at s, g3 into the rho D and pressure adjoints.
+template <int NS, int D, bool FIXED>
+__global__ __launch_bounds__(256) void k_adj_g2(const BoxDev *__restrict__ boxes,
+                                                const Item *__restrict__ items, int nitems, TileShape ts,
+                                                const double *__restrict__ Pbase,
+                                                const double *__restrict__ Vbase,
+                                                const double *__restrict__ coef, AdjBufs ab,
+                                                const DevMech *__restrict__ m) {
+  using L = Layout<NS>;
+  constexpr int NU = L::NU, NP = L::NP;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    const Gather<D> g(b, x, y, z);
+    if (!g.ok) continue;
+    const long long nS = g.nS, nI = g.nI;
+    const int s = g.s;
+    const double *P = Pbase + b.offS * NP;
+    const double *V = Vbase + b.offI * NU;
+    const double *C = coef + b.offI * CF_N;
+    double *Pb = ab.Pb + b.offS * NP;
+    const double idx = b.idx[D], idx2 = b.idx2[D];
+    double dw[9];
+    d1w(idx, dw);
+    double rdW[17], W[17];
+    g.window(P + L::PRD * nS, rdW);
+    double wpS[9], R[9], v4[9], dvb[9], vc[9], cvb[9];
+    {
+      g.window(P + L::PP * nS, W);
+      const double f = rdW[8] / W[8];
+#pragma unroll
+      for (int o = 0; o < 9; ++o) {
+        wpS[o] = f * brow<FIXED>(m, W, o);   // rho D (B p) / p of output cell j_o at s
+        R[o] = bcol<FIXED>(m, rdW, o);
+        cvb[o] = g.at(C + CF_VCB * nI, o) * rdW[12 - o];   // Vcbar rho D at j_o
+        v4[o] = g.at(V + 4 * nI, o);
+        dvb[o] = g.at(C + CF_DIVVCB * nI, o);
+        vc[o] = g.at(C + CF_VC * nI, o);
+      }
+    }
+    const double rds = rdW[8];
+    const bool self = g.valid(4);
+    const double divVc_s = self ? C[CF_DIVVC * nI + g.j(4)] : 0.0;
+    const double Dpp_s = self ? C[CF_DPP * nI + g.j(4)] : 0.0;
+#pragma unroll 1
+    for (int k = 0; k < NS; ++k) {
+      const double iLe = m->invLe[k], c1 = iLe * idx2;
+      double hW[17], vbk[9];
+      g.window(P + (L::PH + k) * nS, hW);
+      const double hs = hW[8];
+#pragma unroll
+      for (int o = 0; o < 9; ++o) vbk[o] = g.at(V + (5 + k) * nI, o);
+      const double Ys = P[(L::PY + k) * nS + s], ds = P[(L::PX + k) * nS + s] - Ys;
+      double Xb = 0.0, Yb = 0.0, hb = 0.0;
+      g.window(P + (L::PX + k) * nS, W);
+#pragma unroll
+      for (int o = 0; o < 9; ++o) hb += v4[o] * c1 * rds * brow<FIXED>(m, W, o);
+#pragma unroll
+      for (int mm = 0; mm < 17; ++mm) W[mm] = rdW[mm] * hW[mm];
+#pragma unroll
+      for (int o = 0; o < 9; ++o) {
+        const double Lhb = v4[o] * c1, Lxb = (vbk[o] - dvb[o]) * c1, e = Lxb + Lhb * hs;
+        const double cv = cvb[o] * iLe;
+        Xb += -cv * dw[o] + e * wpS[o] + Lxb * R[o] + Lhb * bcol<FIXED>(m, W, o);
+        Yb += vc[o] * dw[o] * (vbk[o] + v4[o] * hs) - e * wpS[o];
+        hb += v4[o] * vc[o] * dw[o] * Ys + Lhb * ds * wpS[o];
+      }
+      if (self) {
+        const double cv4 = cvb[4] * iLe;
+        Xb -= cv4 * Dpp_s;
+        Yb += (vbk[4] + v4[4] * hs) * divVc_s + cv4 * Dpp_s;
+        hb += v4[4] * Ys * divVc_s;
+      }
+      Pb[(L::PX + k) * nS + s] += Xb;
+      Pb[(L::PY + k) * nS + s] += Yb;
+      Pb[(L::PH + k) * nS + s] += hb;
+    }
+  }
+}
+
+template <int NS, int D, bool FIXED>
+__global__ __launch_bounds__(256) void k_adj_g3(const BoxDev *__restrict__ boxes,
+                                                const Item *__restrict__ items, int nitems, TileShape ts,
+                                                const double *__restrict__ Pbase,
+                                                const double *__restrict__ Vbase,
+                                                const double *__restrict__ coef, AdjBufs ab,
+                                                const DevMech *__restrict__ m) {
+  using L = Layout<NS>;
+  constexpr int NU = L::NU, NP = L::NP;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    const Gather<D> g(b, x, y, z);
+    if (!g.ok) continue;
+    const long long nS = g.nS, nI = g.nI;
+    const int s = g.s;
+    const double *P = Pbase + b.offS * NP;
+    const double *V = Vbase + b.offI * NU;
+    const double *C = coef + b.offI * CF_N;
+    double *Pb = ab.Pb + b.offS * NP;
+    const double idx = b.idx[D], idx2 = b.idx2[D];
+    double dw[9];
+    d1w(idx, dw);
+    double rpW[17], W[17];   // rho D / p window, scratch window
+    double BP[9], v4[9], dvb[9];
+    double rds, ips;
+    {
+      double pW[17];
+      g.window(P + L::PP * nS, pW);
+      g.window(P + L::PRD * nS, W);
+      rds = W[8];
+      ips = 1.0 / pW[8];
+#pragma unroll
+      for (int mm = 0; mm < 17; ++mm) rpW[mm] = W[mm] / pW[mm];
+#pragma unroll
+      for (int o = 0; o < 9; ++o) {
+        BP[o] = brow<FIXED>(m, pW, o);   // (B p)_o of output cell j_o
+        v4[o] = g.at(V + 4 * nI, o);
+        dvb[o] = g.at(C + CF_DIVVCB * nI, o);
+      }
+    }
+    double wpb[9];
+#pragma unroll
+    for (int o = 0; o < 9; ++o) wpb[o] = 0.0;
+    double rdb = 0.0, pb = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < NS; ++k) {
+      const double iLe = m->invLe[k], c1 = iLe * idx2;
+      double hW[17], vbk[9];
+      g.window(P + (L::PH + k) * nS, hW);
+      const double hs = hW[8];
+#pragma unroll
+      for (int o = 0; o < 9; ++o) vbk[o] = g.at(V + (5 + k) * nI, o);
+      // (B X_k) rows
+      g.window(P + (L::PX + k) * nS, W);
+#pragma unroll
+      for (int o = 0; o < 9; ++o) rdb += brow<FIXED>(m, W, o) * ((vbk[o] - dvb[o]) * c1 + v4[o] * c1 * hs);
+      // d = X_k - Y_k, then d rho D / p and h_k d rho D / p
+      {
+        double YW[17];
+        g.window(P + (L::PY + k) * nS, YW);
+#pragma unroll
+        for (int mm = 0; mm < 17; ++mm) W[mm] -= YW[mm];
+      }
+      const double ds = W[8];
+#pragma unroll
+      for (int mm = 0; mm < 17; ++mm) {
+        W[mm] *= rpW[mm];
+        hW[mm] *= W[mm];
+      }
+#pragma unroll
+      for (int o = 0; o < 9; ++o) {
+        const double Lhb = v4[o] * c1, Lxb = (vbk[o] - dvb[o]) * c1;
+        wpb[o] += (Lxb + Lhb * hs) * ds;
+        pb += Lxb * bcol<FIXED>(m, W, o) + Lhb * bcol<FIXED>(m, hW, o);
+      }
+    }
+    // rho D (B p) / p and D p / p of the output cells (p at j_o = rho D / (rho D / p))
+#pragma unroll
+    for (int o = 0; o < 9; ++o) {
+      const double wpS = rds * BP[o] * ips;
+      rdb += wpb[o] * BP[o] * ips;
+      const double pj = P[L::PP * nS + min(max(s + (4 - o) * g.st, g.lo), g.hi)];
+      pb += g.at(C + CF_DPPB * nI, o) * dw[o] / pj - wpb[o] * wpS * ips;
+    }
+    if (g.valid(4)) {
+      rdb += C[CF_RDSELF * nI + g.j(4)];
+      pb -= C[CF_DPPB * nI + g.j(4)] * C[CF_DPP * nI + g.j(4)] * ips;
+    }
+    Pb[L::PRD * nS + s] += rdb;
+    Pb[L::PP * nS + s] += pb;
   }
 }
 
@@ -599,14 +820,22 @@ __global__ __launch_bounds__(256) void k_fold(const BoxDev *__restrict__ boxes,
   }
 }
 
-// lnA_bar[j] += sum over workgroups of partial[block][j], in block order.
+// lnA_bar[j] += sum over workgroups of partial[block][j]: workgroup j sums
+// reaction j's partials, thread t taking blocks t, t + 256, ... in order,
+// then a fixed binary tree over the threads (deterministic).
 __global__ __launch_bounds__(256) void k_lnA_reduce(const double *__restrict__ partial, int nblocks,
                                                     int nr, double *__restrict__ lnA_bar) {
-  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
-    double s = 0.0;
-    for (int q = 0; q < nblocks; ++q) s += partial[(long long)q * nr + j];
-    lnA_bar[j] += s;
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nblocks; q += 256) s += partial[(long long)q * nr + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) lnA_bar[j] += red[0];
 }
 
 // ------------------------------------------------------------------ launches
@@ -618,29 +847,41 @@ static inline int flat_grid(long long n) {
 
 template <int NS>
 struct AdjLaunch {
-  template <bool FIXED>
-  static void dir_t(const LaunchCtx &c, const AdjItems &ai, int d, int phase, const double *U,
-                    const double *P, const double *G, const double *V, const AdjBufs &ab, unsigned parts) {
-    const dim3 grid(grid_of(ai.n[d], c.cap)), block(ai.ts[d].tx * ai.ts[d].ty * ai.ts[d].tz);
-    const Item *items = ai.items[d];
-    prof_begin(c.prof, K_DIR_ADJ_X + d, c.stream);
-    if (d == 0)
-      hipLaunchKernelGGL((k_dir_adj<NS, 0, FIXED>), grid, block, 0, c.stream, c.boxes, items, ai.n[d], ai.ts[d],
-                         phase, U, P, G, V, ab, parts, c.mech);
-    else if (d == 1)
-      hipLaunchKernelGGL((k_dir_adj<NS, 1, FIXED>), grid, block, 0, c.stream, c.boxes, items, ai.n[d], ai.ts[d],
-                         phase, U, P, G, V, ab, parts, c.mech);
-    else
-      hipLaunchKernelGGL((k_dir_adj<NS, 2, FIXED>), grid, block, 0, c.stream, c.boxes, items, ai.n[d], ai.ts[d],
-                         phase, U, P, G, V, ab, parts, c.mech);
-    prof_end(c.prof, K_DIR_ADJ_X + d, c.stream);
+  template <int D, bool FIXED>
+  static void dir_dt(const LaunchCtx &c, const double *U, const double *P, const double *G, const double *V,
+                     const AdjBufs &ab, double *coef, unsigned parts) {
+    const dim3 gI(grid_of(c.nI, c.cap)), bI(c.tsI.tx * c.tsI.ty * c.tsI.tz);
+    const dim3 gS(grid_of(c.nS, c.cap)), bS(c.tsS.tx * c.tsS.ty * c.tsS.tz);
+    prof_begin(c.prof, K_DIR_ADJ_X + D, c.stream);
+    if (parts & 2)
+      hipLaunchKernelGGL((k_adj_coef<NS, D, FIXED>), gI, bI, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, P, V,
+                         coef, c.mech);
+    hipLaunchKernelGGL((k_adj_g1<NS, D, FIXED>), gS, bS, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, G, V,
+                       ab, parts, c.mech);
+    if (parts & 2) {
+      hipLaunchKernelGGL((k_adj_g2<NS, D, FIXED>), gS, bS, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, V,
+                         coef, ab, c.mech);
+      hipLaunchKernelGGL((k_adj_g3<NS, D, FIXED>), gS, bS, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, V,
+                         coef, ab, c.mech);
+    }
+    prof_end(c.prof, K_DIR_ADJ_X + D, c.stream);
   }
-  static void dir(const LaunchCtx &c, const AdjItems &ai, int d, int phase, const double *U, const double *P,
-                  const double *G, const double *V, const AdjBufs &ab, unsigned parts) {
-    if (c.smc_stencil)
-      dir_t<true>(c, ai, d, phase, U, P, G, V, ab, parts);
+  template <bool FIXED>
+  static void dir_t(const LaunchCtx &c, int d, const double *U, const double *P, const double *G,
+                    const double *V, const AdjBufs &ab, double *coef, unsigned parts) {
+    if (d == 0)
+      dir_dt<0, FIXED>(c, U, P, G, V, ab, coef, parts);
+    else if (d == 1)
+      dir_dt<1, FIXED>(c, U, P, G, V, ab, coef, parts);
     else
-      dir_t<false>(c, ai, d, phase, U, P, G, V, ab, parts);
+      dir_dt<2, FIXED>(c, U, P, G, V, ab, coef, parts);
+  }
+  static void dir(const LaunchCtx &c, int d, const double *U, const double *P, const double *G,
+                  const double *V, const AdjBufs &ab, double *coef, unsigned parts) {
+    if (c.smc_stencil)
+      dir_t<true>(c, d, U, P, G, V, ab, coef, parts);
+    else
+      dir_t<false>(c, d, U, P, G, V, ab, coef, parts);
   }
   static int chem(const LaunchCtx &c, const double *U, const double *V, const AdjBufs &ab, double *partial) {
     const int grid = grid_of(c.nI, c.cap);
@@ -687,7 +928,7 @@ void adj_lincomb(const LaunchCtx &c, const LincombArgs &a, double *Y, long long 
 }
 void adj_lnA_reduce(const LaunchCtx &c, const double *partial, int nblocks, int nr, double *lnA_bar) {
   prof_begin(c.prof, K_ADJ_LINALG, c.stream);
-  hipLaunchKernelGGL(k_lnA_reduce, dim3(1), dim3(256), 0, c.stream, partial, nblocks, nr, lnA_bar);
+  hipLaunchKernelGGL(k_lnA_reduce, dim3(nr), dim3(256), 0, c.stream, partial, nblocks, nr, lnA_bar);
   prof_end(c.prof, K_ADJ_LINALG, c.stream);
 }
 

@@ -121,16 +121,10 @@ struct Plan {
   int cap = 0;                 // workgroups per launch (0: one per work item)
   double **d_Utab = nullptr;
   std::vector<double *> Uptrs;
-  // work lists of the direction adjoint kernels (built on first use)
-  Item *d_adj = nullptr;
-  int nA[3] = {0, 0, 0};
-  size_t adj_off[3] = {0, 0, 0};
-  TileShape tsA[3]{};
   ~Plan() {
     if (d_boxes) (void)hipFree(d_boxes);
     if (d_items) (void)hipFree(d_items);
     if (d_Utab) (void)hipFree(d_Utab);
-    if (d_adj) (void)hipFree(d_adj);
   }
 };
 
@@ -1090,69 +1084,16 @@ const char *sdc_kernel_name(int id) { return (id >= 0 && id < K_NKERNELS) ? KERN
 // ================================================================ adjoint
 namespace {
 
-// tile shape for a (compressed) index space of extents a, b, c: 256 threads
-TileShape adj_tile(int a, int b) {
-  auto p2 = [](int v, int cap) {
-    int t = 1;
-    while (t < v && t < cap) t <<= 1;
-    return t;
-  };
-  TileShape t;
-  t.tx = p2(a, 64);
-  t.ty = p2(b, 256 / t.tx);
-  t.tz = 256 / (t.tx * t.ty);
-  return t;
-}
-
 int grid_cap_of(const sdc_context *c, const Plan *p) {
   return c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : 1 << 30);
 }
 
-// Work lists of the direction adjoint kernels: for direction D the interior
-// cells with the D coordinate divided by nine (rounded up).
-int adj_items(sdc_context *c, Plan *p, AdjItems &ai) {
-  if (!p->d_adj) {
-    std::vector<Item> all;
-    for (int d = 0; d < 3; ++d) {
-      int mx = 0, my = 0;
-      for (const box_desc &b : p->boxes) {
-        int n[3] = {b.nx, b.ny, b.nz};
-        n[d] = (n[d] + 8) / 9;
-        mx = std::max(mx, n[0]);
-        my = std::max(my, n[1]);
-      }
-      const TileShape ts = adj_tile(mx, my);
-      p->tsA[d] = ts;
-      p->adj_off[d] = all.size();
-      std::vector<Item> nat;
-      for (int bi = 0; bi < p->nbox; ++bi) {
-        const box_desc &b = p->boxes[bi];
-        int n[3] = {b.nx, b.ny, b.nz};
-        n[d] = (n[d] + 8) / 9;
-        for (int z = 0; z < n[2]; z += ts.tz)
-          for (int y = 0; y < n[1]; y += ts.ty)
-            for (int x = 0; x < n[0]; x += ts.tx) nat.push_back(Item{bi, x, y, z});
-      }
-      const std::vector<Item> o = xcd_order(nat, std::min<long long>((long long)nat.size(), grid_cap_of(c, p)));
-      all.insert(all.end(), o.begin(), o.end());
-      p->nA[d] = (int)(all.size() - p->adj_off[d]);
-    }
-    HIPCHECK(c, hipMalloc(&p->d_adj, sizeof(Item) * all.size()));
-    HIPCHECK(c, hipMemcpy(p->d_adj, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice));
-  }
-  for (int d = 0; d < 3; ++d) {
-    ai.items[d] = p->d_adj + p->adj_off[d];
-    ai.n[d] = p->nA[d];
-    ai.ts[d] = p->tsA[d];
-  }
-  return SDC_OK;
-}
-
 // scratch of one vector-Jacobian product (doubles): primitive fields and
-// velocity gradient of the forward evaluation, then the adjoint
-// accumulators (contiguous, cleared together) and the ln A partials
+// velocity gradient of the forward evaluation, the adjoint accumulators
+// (contiguous, cleared together), the per-cell coefficient table of the
+// direction adjoints and the ln A partials
 struct VjpLayout {
-  size_t P, G, Pb, Gb, Ub, part, total;
+  size_t P, G, Pb, Gb, Ub, coef, part, total;
 };
 VjpLayout vjp_layout(const Plan *p, int ns, int nr, int cap) {
   VjpLayout w{};
@@ -1168,6 +1109,7 @@ VjpLayout vjp_layout(const Plan *p, int ns, int nr, int cap) {
   w.Pb = take((size_t)p->totS * nP);
   w.Gb = take((size_t)p->totS * 9);
   w.Ub = take((size_t)p->totS * nU);
+  w.coef = take((size_t)p->totI * 7);
   const int nblk = std::max(1, std::min(p->nI, cap));
   w.part = take((size_t)nblk * std::max(nr, 1));
   w.total = off;
@@ -1182,9 +1124,6 @@ int rhs_vjp_g(sdc_context *c, Plan *p, const LaunchCtx &l, double *U, const doub
   const AdjOps *a = adj_ops_for(o->ns);
   const int ns = o->ns, nU = 5 + ns;
   const VjpLayout L = vjp_layout(p, ns, c->h_mech.nr, grid_cap_of(c, p));
-  AdjItems ai;
-  int rc = adj_items(c, p, ai);
-  if (rc) return rc;
   double *P = W + L.P, *G = W + L.G;
   const FRef Uf{U, nullptr};
   o->ghost(l, Uf);
@@ -1192,13 +1131,8 @@ int rhs_vjp_g(sdc_context *c, Plan *p, const LaunchCtx &l, double *U, const doub
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
   adj_fill0(l, W + L.Pb, (long long)(L.Ub - L.Pb) + (long long)p->totS * nU);
   const AdjBufs ab{W + L.Ub, W + L.Pb, W + L.Gb};
-  if (parts & RHS_AD) {
-    for (int d = 0; d < 3; ++d) {
-      int nmax = 0;
-      for (const box_desc &b : p->boxes) nmax = std::max(nmax, d == 0 ? b.nx : (d == 1 ? b.ny : b.nz));
-      for (int r = 0; r < 9 && r < nmax; ++r) a->dir(l, ai, d, r, U, P, G, V, ab, parts & RHS_AD);
-    }
-  }
+  if (parts & RHS_AD)
+    for (int d = 0; d < 3; ++d) a->dir(l, d, U, P, G, V, ab, W + L.coef, parts & RHS_AD);
   int nblk = 0;
   if (parts & RHS_REACT) nblk = a->chem(l, U, V, ab, W + L.part);
   if (parts & RHS_DIFF) a->vgrad(l, ab);
