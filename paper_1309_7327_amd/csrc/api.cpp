@@ -118,6 +118,8 @@ struct Plan {
   Item *d_items = nullptr;   // interior, stored, ghost, interior-y, interior-z lists back to back
   int nI = 0, nS = 0, nG = 0;
   TileShape tsI{}, tsS{};
+  TileShape tsZ{};             // tile of the z stencil pass
+  int nZ = 0;                  // its work items
   int cap = 0;                 // workgroups per launch (0: one per work item)
   double **d_Utab = nullptr;
   std::vector<double *> Uptrs;
@@ -321,6 +323,10 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
   p->boxes.assign(bx, bx + nbox);
   p->tsI = tI;
   p->tsS = tS;
+  // the z pass takes the interior tile with its y and z extents exchanged:
+  // its waves then share the z-lines' planes
+  const TileShape tZ{tI.tx, tI.tz, tI.ty};
+  p->tsZ = tZ;
   p->cap = cap;
   std::vector<BoxDev> hb(nbox);
   std::vector<Item> iI, iS, iG, iY, iZ;
@@ -345,9 +351,9 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
     for (int z = 0; z < d.nz; z += tI.tz)
       for (int x = 0; x < d.nx; x += tI.tx)
         for (int y = 0; y < d.ny; y += tI.ty) iY.push_back(Item{b, x, y, z});
-    for (int y = 0; y < d.ny; y += tI.ty)
-      for (int x = 0; x < d.nx; x += tI.tx)
-        for (int z = 0; z < d.nz; z += tI.tz) iZ.push_back(Item{b, x, y, z});
+    for (int y = 0; y < d.ny; y += tZ.ty)
+      for (int x = 0; x < d.nx; x += tZ.tx)
+        for (int z = 0; z < d.nz; z += tZ.tz) iZ.push_back(Item{b, x, y, z});
     for (int z = 0; z < d.sz; z += tS.tz)
       for (int y = 0; y < d.sy; y += tS.ty)
         for (int x = 0; x < d.sx; x += tS.tx) iS.push_back(Item{b, x, y, z});
@@ -357,6 +363,7 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
   p->nI = (int)iI.size();
   p->nS = (int)iS.size();
   p->nG = (int)iG.size();
+  p->nZ = (int)iZ.size();
   const long long capE = c->grid_cap > 0 ? c->grid_cap : (cap > 0 ? cap : (1LL << 30));
   std::vector<Item> all;
   for (const std::vector<Item> *v : {&iI, &iS, &iG, &iY, &iZ}) {
@@ -387,6 +394,10 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.itemsD[0] = l.itemsI;
   l.itemsD[1] = l.itemsG + p->nG;
   l.itemsD[2] = l.itemsD[1] + p->nI;
+  l.nD[0] = l.nD[1] = p->nI;
+  l.nD[2] = p->nZ;
+  l.tsD[0] = l.tsD[1] = p->tsI;
+  l.tsD[2] = p->tsZ;
   l.nI = p->nI;
   l.nS = p->nS;
   l.nG = p->nG;
@@ -400,10 +411,13 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   return l;
 }
 
-// One right-hand-side evaluation into F (interior) from U (ghosted).
-void eval_rhs_g(const Ops *o, const LaunchCtx &l, FRef U, double *P, double *G, FRef F, unsigned parts) {
+// One right-hand-side evaluation into F (interior) from U (ghosted).  warm:
+// P holds the previous evaluation of the same boxes (its temperatures start
+// the Newton solves).
+void eval_rhs_g(const Ops *o, const LaunchCtx &l, FRef U, double *P, double *G, FRef F, unsigned parts,
+                bool warm = false) {
   o->ghost(l, U);
-  o->prims(l, U, P, F, (parts & RHS_REACT) ? 2 : 1);
+  o->prims(l, U, P, F, (parts & RHS_REACT) ? 2 : 1, warm ? 1 : 0);
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
   if (parts & RHS_AD) {
     for (int d = 0; d < 3; ++d) o->dir(l, d, U, P, G, F, parts & RHS_AD);
@@ -531,7 +545,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
         for (int m = 1; m <= M; ++m) Fnew[m] = (k % 2 == 0) ? FA[m] : FB[m];
         FRef Ucur = Uuser;
         for (int m = 0; m < M; ++m) {
-          if (m > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL);
+          if (m > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL, true);
           FRef Unext = (m == M - 1 && k == K - 1) ? Uuser : Ub[m % 2];
           NodeArgs a{};
           for (int j = 0; j <= M; ++j) {
@@ -547,7 +561,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
           Ucur = Unext;
         }
         const bool last = step == nsteps - 1 && k == K - 1;
-        if (!last) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL);
+        if (!last) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL, true);
         for (int j = 0; j <= M; ++j) Fold[j] = Fnew[j];
       }
       if (step < nsteps - 1) {
@@ -602,7 +616,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
       FRef Uout = Ucur;
       for (int pi = 0; pi < M; ++pi) {
         FRef Uin = pi == 0 ? Uuser : Ucur;
-        if (pi > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{F1p(F1new[pi]), nullptr}, RHS_AD);
+        if (pi > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{F1p(F1new[pi]), nullptr}, RHS_AD, true);
         Uout = (k == K - 1 && pi == M - 1) ? Uuser : Ucur;
         FinePtrs fp{};
         fp.F1base = F1base;
@@ -622,7 +636,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
         fp.dt = dt;
         o->mr_fine(l, Uin, Uout, c->d_fine + pi, fp, W + L.A, fI);
       }
-      if (!last) eval_rhs_g(o, l, Uout, P, G, FRef{F1p(F1new[M]), nullptr}, RHS_AD);
+      if (!last) eval_rhs_g(o, l, Uout, P, G, FRef{F1p(F1new[M]), nullptr}, RHS_AD, true);
       F1old = F1new;
       F2old = F2new;
     }
@@ -1127,7 +1141,7 @@ int rhs_vjp_g(sdc_context *c, Plan *p, const LaunchCtx &l, double *U, const doub
   double *P = W + L.P, *G = W + L.G;
   const FRef Uf{U, nullptr};
   o->ghost(l, Uf);
-  o->prims(l, Uf, P, FRef{nullptr, nullptr}, 0);
+  o->prims(l, Uf, P, FRef{nullptr, nullptr}, 0, 0);
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
   adj_fill0(l, W + L.Pb, (long long)(L.Ub - L.Pb) + (long long)p->totS * nU);
   const AdjBufs ab{W + L.Ub, W + L.Pb, W + L.Gb};
@@ -1209,7 +1223,7 @@ void sdc_forward_record(const Ops *o, const LaunchCtx &l, double *X, double dt, 
     for (int m = 1; m <= M; ++m) Fnew[m] = (k % 2 == 0) ? FA[m] : FB[m];
     FRef Ucur{X, nullptr};
     for (int m = 0; m < M; ++m) {
-      if (m > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL);
+      if (m > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL, true);
       FRef Unext{nodes + fS * ((long long)k * M + m), nullptr};
       NodeArgs a{};
       for (int j = 0; j <= M; ++j) {
@@ -1224,7 +1238,7 @@ void sdc_forward_record(const Ops *o, const LaunchCtx &l, double *X, double dt, 
       o->sdc_node(l, Ucur, Unext, a);
       Ucur = Unext;
     }
-    if (k < K - 1) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL);
+    if (k < K - 1) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL, true);
     for (int j = 0; j <= M; ++j) Fold[j] = Fnew[j];
   }
 }

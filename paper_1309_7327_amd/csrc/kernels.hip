@@ -125,12 +125,14 @@ __global__ __launch_bounds__(256) void k_ghost(const BoxDev *__restrict__ boxes,
   }
 }
 
-// out_mode: 0 leave the right-hand side alone, 1 zero it, 2 chemistry source
+// out_mode: 0 leave the right-hand side alone, 1 zero it, 2 chemistry source.
+// warm != 0: start the Newton solve from the temperature the previous
+// evaluation left in P (when it lies in the fit range), else from 1000 K.
 template <int NS>
 __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
                                                TileShape ts, FRef Uref, double *__restrict__ Pbase,
-                                               FRef Fout, int out_mode,
+                                               FRef Fout, int out_mode, int warm,
                                                const DevMech *__restrict__ m, int *err) {
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
@@ -150,7 +152,12 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
 #pragma unroll
     for (int q = 0; q < NU; ++q) Uc[q] = U[q * nS + s];
     double rho, u[3], Y[NS], T;
-    const int e = cell_state<NS>(m, Uc, rho, u, Y, T);
+    double T0 = 1000.0;
+    if (warm) {
+      const double Tp = P[L::PT * nS + s];
+      if (Tp >= m->Tlo && Tp <= m->Thi) T0 = Tp;
+    }
+    const int e = cell_state<NS>(m, Uc, rho, u, Y, T, T0);
     if (e) atomicOr(err, e);
     const double invT = 1.0 / T;
     double sumYW = 0.0, cp = 0.0;
@@ -705,10 +712,10 @@ struct Launch {
                        c.itemsG, c.nG, U);
     prof_end(c.prof, K_GHOST, c.stream);
   }
-  static void prims(const LaunchCtx &c, FRef U, double *P, FRef F, int out_mode) {
+  static void prims(const LaunchCtx &c, FRef U, double *P, FRef F, int out_mode, int warm) {
     prof_begin(c.prof, K_PRIMS, c.stream);
     hipLaunchKernelGGL(k_prims<NS>, dim3(grid_for(c.nS, c.cap)), dim3(c.tsS.tx * c.tsS.ty * c.tsS.tz), 0,
-                       c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F, out_mode, c.mech, c.err);
+                       c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F, out_mode, warm, c.mech, c.err);
     prof_end(c.prof, K_PRIMS, c.stream);
   }
   static void vgrad(const LaunchCtx &c, const double *P, double *G) {
@@ -720,16 +727,17 @@ struct Launch {
   template <bool FIXED>
   static void dir_t(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F,
                     unsigned parts) {
-    const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
+    const TileShape ts = c.tsD[d];
+    const dim3 grid(grid_for(c.nD[d], c.cap)), block(ts.tx * ts.ty * ts.tz);
     prof_begin(c.prof, K_DIR_X + d, c.stream);
     if (d == 0)
-      hipLaunchKernelGGL((k_dir<NS, 0, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nI, c.tsI, U, P,
+      hipLaunchKernelGGL((k_dir<NS, 0, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nD[0], ts, U, P,
                          G, F, parts, c.mech);
     else if (d == 1)
-      hipLaunchKernelGGL((k_dir<NS, 1, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nI, c.tsI, U, P,
+      hipLaunchKernelGGL((k_dir<NS, 1, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nD[1], ts, U, P,
                          G, F, parts, c.mech);
     else
-      hipLaunchKernelGGL((k_dir<NS, 2, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nI, c.tsI, U, P,
+      hipLaunchKernelGGL((k_dir<NS, 2, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nD[2], ts, U, P,
                          G, F, parts, c.mech);
     prof_end(c.prof, K_DIR_X + d, c.stream);
   }

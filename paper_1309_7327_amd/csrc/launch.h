@@ -28,7 +28,9 @@ struct LaunchCtx {
   hipStream_t stream;
   const BoxDev *boxes;
   const Item *itemsI, *itemsS, *itemsG;
-  const Item *itemsD[3];   // the interior list ordered with direction D fastest
+  const Item *itemsD[3];   // interior lists of the stencil passes, direction D fastest
+  int nD[3];
+  TileShape tsD[3];
   int nI, nS, nG;
   TileShape tsI, tsS;
   int cap;
@@ -43,7 +45,7 @@ struct Ops {
   void (*prim_to_cons)(const LaunchCtx &, const double *, const double *, const double *,
                        const double *, FRef);
   void (*ghost)(const LaunchCtx &, FRef);
-  void (*prims)(const LaunchCtx &, FRef, double *, FRef, int);
+  void (*prims)(const LaunchCtx &, FRef, double *, FRef, int out_mode, int warm);
   void (*vgrad)(const LaunchCtx &, const double *, double *);
   void (*dir)(const LaunchCtx &, int, FRef, const double *, const double *, FRef, unsigned);
   void (*chem)(const LaunchCtx &, FRef, double *);
