@@ -240,10 +240,10 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
   }
 }
 
-// Occupancy: three workgroups per CU along x (a small spill), two along y
-// and z (whose larger spill costs more than the extra waves gain).
+// Occupancy: three workgroups per CU along x for up to 9 species (a small
+// spill), two otherwise (larger spills cost more than the extra waves gain).
 template <int NS, int D, bool FIXED>
-__global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
+__global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
                                              TileShape ts, FRef Uref,
                                              const double *__restrict__ Pbase,
@@ -256,6 +256,10 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
   // 36 KiB per workgroup)
   constexpr bool SPEC_LDS = NS <= 9;
   __shared__ double spec_sh[SPEC_LDS ? 2 * NS * 256 : 1];
+  // more species: their accumulators live in the thread's LDS column (a
+  // register array indexed by the species loop would fall to scratch)
+  constexpr bool ACC_LDS = !SPEC_LDS;
+  __shared__ double acc_sh[ACC_LDS ? NS * 256 : 1];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -274,9 +278,21 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
     const double *G = Gbase + b.offS * 9;
     double *F = Fout.get(w.box, b.offI * NU);
     const double idx = b.idx[D], idx2 = b.idx2[D];
-    double acc[NU];
+    double acc[ACC_LDS ? 5 : NU];
 #pragma unroll
-    for (int q = 0; q < NU; ++q) acc[q] = 0.0;
+    for (int q = 0; q < (ACC_LDS ? 5 : NU); ++q) acc[q] = 0.0;
+    double *asp = acc_sh + threadIdx.x;
+    if constexpr (ACC_LDS) {
+#pragma unroll 1
+      for (int k = 0; k < NS; ++k) asp[k * 256] = 0.0;
+    }
+    // species accumulator k
+    auto spc = [&](int k) -> double & {
+      if constexpr (ACC_LDS)
+        return asp[k * 256];
+      else
+        return acc[5 + k];
+    };
     auto line = [&](const double *f, double *v) {
 #pragma unroll
       for (int o = 0; o < 9; ++o) v[o] = (f + (o - 4) * st)[s];
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
 #pragma unroll 1
         for (int k = 0; k < NS; ++k) {
           line(U + (5 + k) * nS, f);
-          acc[5 + k] -= d1p(f, ud, idx);
+          spc(k) -= d1p(f, ud, idx);
         }
       }
     }
@@ -394,7 +410,7 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
             double y9[9];
             if (HYP_IN_SPECIES && (parts & 1)) {
               line(U + (5 + k) * nS, y9);
-              acc[5 + k] -= d1p(y9, ud, idx);
+              spc(k) -= d1p(y9, ud, idx);
             }
             line(P + (L::PX + k) * nS, u9);
             line(P + (L::PY + k) * nS, y9);
@@ -413,7 +429,7 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
               Lpe += u9[o] * g[o] * wp[o];
             }
             const double t = iLe * (Lx + Lp) * idx2;
-            acc[5 + k] += t;
+            spc(k) += t;
             divVc -= t;
             acc[4] += iLe * (LhX + Lpe) * idx2;
             Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
@@ -424,7 +440,7 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
           }
           // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart
 #pragma unroll
-          for (int k = 0; k < NS; ++k) acc[5 + k] += ysh[k * 256] * divVc + Vc * ysh[(NS + k) * 256];
+          for (int k = 0; k < NS; ++k) spc(k) += ysh[k * 256] * divVc + Vc * ysh[(NS + k) * 256];
           acc[4] += ShY * divVc + Vc * SDhY;
         } else {
 #pragma unroll 1
@@ -432,7 +448,7 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
             const double iLe = m->invLe[k];
             if (HYP_IN_SPECIES && (parts & 1)) {
               line(U + (5 + k) * nS, u9);
-              acc[5 + k] -= d1p(u9, ud, idx);
+              spc(k) -= d1p(u9, ud, idx);
             }
             line(P + (L::PX + k) * nS, u9);
             bvec<FIXED>(m, u9, v);
@@ -451,7 +467,7 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
               Lpe += u9[o] * g[o] * wp[o];
             }
             const double t = iLe * (Lx + Lp) * idx2;
-            acc[5 + k] += t;
+            spc(k) += t;
             divVc -= t;
             acc[4] += iLe * (LhX + Lpe) * idx2;
             Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
@@ -463,14 +479,21 @@ __global__ __launch_bounds__(256, D == 0 ? 3 : 2) void k_dir(const BoxDev *__res
             line(P + (L::PH + k) * nS, g);
             const double DY = d1(u9, idx);
             const double DhY = d1p(g, u9, idx);
-            acc[5 + k] += u9[4] * divVc + Vc * DY;
+            spc(k) += u9[4] * divVc + Vc * DY;
             acc[4] += g[4] * u9[4] * divVc + Vc * DhY;
           }
         }
       }
     }
+    if constexpr (ACC_LDS) {
 #pragma unroll
-    for (int q = 0; q < NU; ++q) (F + q * nI)[i] += acc[q];
+      for (int q = 0; q < 5; ++q) (F + q * nI)[i] += acc[q];
+#pragma unroll 1
+      for (int k = 0; k < NS; ++k) (F + (5 + k) * nI)[i] += spc(k);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NU; ++q) (F + q * nI)[i] += acc[q];
+    }
   }
 }
 
