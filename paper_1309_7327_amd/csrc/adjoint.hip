@@ -609,7 +609,7 @@ __global__ __launch_bounds__(256) void k_chem_adj(const BoxDev *__restrict__ box
     const int e = cell_state<NS>(m, Uc, rho, u, Y, T);
     if (e && act) atomicOr(err, e);
     const double lnT = log(T), invT = 1.0 / T;
-    const double lnRTp = log(RU * T / PREF);
+    const double lnRTp = lnT + LN_RU_PREF;
     double c[NS + 1], g[NS + 1], hr[NS + 1], wb[NS + 1], cb[NS + 1];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {

@@ -11,6 +11,7 @@ namespace nsdc {
 
 constexpr double RU = 8.31446261815324;
 constexpr double PREF = 101325.0;
+constexpr double LN_RU_PREF = -9.408091968943316;  // ln(RU / PREF)
 // eighth-order centred first-derivative weights
 constexpr double C1 = 4.0 / 5.0, C2 = -1.0 / 5.0, C3 = 4.0 / 105.0, C4 = -1.0 / 280.0;
 
@@ -44,24 +45,34 @@ __device__ __forceinline__ double s_R(const DevMech *__restrict__ m, int k, doub
 // Temperature from the specific internal energy e by Newton's method on
 // e(T) = sum_k Y_k R_k T (h_k/(R_k T) - 1), de/dT = c_v: start at T0 (1000 K
 // unless a nearby temperature is known), stop one iteration after the first
-// update below 1e-12 T (at most 50).
+// update below 1e-12 T (at most 50).  With one NASA-7 range per species e(T)
+// is a quintic in T whose coefficients are the mass-weighted species
+// coefficients, so the mixture is summed once and every iteration evaluates
+// two short polynomials (e and its derivative, which is c_v).
 template <int NS>
 __device__ int temperature(const DevMech *__restrict__ m, const double *Y, double e, double &T,
                            double T0 = 1000.0) {
+  // keep the coefficient loads here: hoisted into an enclosing loop, the
+  // mechanism tables exceed the scalar registers and are spilled
+  asm volatile("" ::: "memory");
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0, c5 = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double YR = Y[k] * m->Rk[k];
+    const double *a = m->hc[k];
+    c0 += YR * (a[0] - 1.0);
+    c1 += YR * a[1];
+    c2 += YR * a[2];
+    c3 += YR * a[3];
+    c4 += YR * a[4];
+    c5 += YR * m->h6[k];
+  }
+  const double d1 = 2.0 * c1, d2 = 3.0 * c2, d3 = 4.0 * c3, d4 = 5.0 * c4;
   T = T0;
   bool conv = false;
   for (int it = 0; it < 50; ++it) {
-    // keep the coefficient loads inside the iteration: hoisted, the
-    // mechanism tables exceed the scalar registers and are spilled
-    asm volatile("" ::: "memory");
-    const double invT = 1.0 / T;
-    double eT = 0.0, cv = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const double YR = Y[k] * m->Rk[k];
-      eT += YR * T * (h_RT(m, k, T, invT) - 1.0);
-      cv += YR * (cp_R(m, k, T) - 1.0);
-    }
+    const double eT = c5 + T * (c0 + T * (c1 + T * (c2 + T * (c3 + T * c4))));
+    const double cv = c0 + T * (d1 + T * (d2 + T * (d3 + T * d4)));
     const double dT = (eT - e) / cv;
     T -= dT;
     if (conv) return (T >= m->Tlo && T <= m->Thi) ? 0 : NSDC_ERR_TRANGE;
@@ -90,7 +101,7 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
   c[NS] = 1.0;
   g[NS] = 0.0;
   w[NS] = 0.0;
-  const double lnRTp = log(RU * T / PREF);
+  const double lnRTp = lnT + LN_RU_PREF;
   const int nr = m->nr;
 #pragma unroll 2
   for (int j = 0; j < nr; ++j) {
@@ -133,7 +144,7 @@ __device__ void production_sh(const DevMech *__restrict__ m, double rho, double 
   sh[NS * S] = 1.0;
   sh[A + NS * S] = 0.0;
   sh[2 * A + NS * S] = 0.0;
-  const double lnRTp = log(RU * T / PREF);
+  const double lnRTp = lnT + LN_RU_PREF;
   const int nr = m->nr;
 #pragma unroll 2
   for (int j = 0; j < nr; ++j) {
