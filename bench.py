@@ -31,7 +31,7 @@ FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # Algorithmic work per cell of each kernel kind (flops, HBM bytes), from the
 # operation counts of the method (not of the implementation): see the
 # measurement section of the design notes.
-def work_model(ns, n_coarse, n_fine_per_interval):
+def work_model(ns, nr, n_coarse, n_fine_per_interval):
     nu = 5 + ns
     np_ = 8 + 3 * ns
     # one direction of the stencil pass: convective divergence, narrow row sums
@@ -41,8 +41,10 @@ def work_model(ns, n_coarse, n_fine_per_interval):
     first = 11 * (36 + 12 * ns) / 3.0
     dir_flops = narrow + first
     dir_bytes = 8 * (nu + np_ + 4 + 2 * nu)            # read U, P, 4 gradients; read+write dU/dt
-    chem_flops = 32 * ns + 75 * (21 if ns == 9 else 84)
-    newton = 5 * ns * 20
+    chem_flops = 32 * ns + 75 * nr
+    # temperature from e: the mixture's six NASA coefficients (12 ns flops),
+    # then three Newton iterations of a quintic, its derivative and the update
+    newton = 12 * ns + 3 * 21
     r = n_fine_per_interval
     n1 = n_coarse
     # fine sub-sweep of one coarse interval: r chemistry sub-steps per cell
@@ -168,14 +170,14 @@ def bench_adjoint(args):
     ctx.profile(False)
     ctx.check_status()
     np_ = 8 + 3 * ns
-    # one direction adjoint launch covers a ninth of the cells; per output
-    # cell it reads the state, primitive and gradient lines and the
-    # cotangent, and updates the three adjoint accumulators
+    # one direction adjoint call (coefficient, gather passes) covers every
+    # cell; per cell it reads the state, the primitive and gradient lines
+    # and the cotangent, and updates the three adjoint accumulators
     by_cell = 8 * (2 * nU + np_ + 4) + 16 * (nU + np_ + 4)
     dirk = [k for k in kern if k.startswith("dir_adj")]
     dominant = max(dirk, key=lambda k: kern[k][0])
     dur_ms = kern[dominant][0] / kern[dominant][1]
-    ach = by_cell * ncell / 9 / (dur_ms * 1e-3) / 1e9
+    ach = by_cell * ncell / (dur_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": stored_traffic(dominant, args.workload), "kernel": dominant, "avg_launch_ms": dur_ms}
     out = {
@@ -273,7 +275,7 @@ def bench_batch(args):
     kern = ctx.profile_read(h)
     ctx.profile(False)
     ctx.check_status(h)
-    model = work_model(ns, sd["n_coarse"], 0)
+    model = work_model(ns, mech["nr"], sd["n_coarse"], 0)
     dominant = max(kern, key=lambda k: kern[k][0])
     dur_ms = kern[dominant][0] / kern[dominant][1]
     roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None}
@@ -384,7 +386,7 @@ def main():
     M1 = sch_d["n_coarse"] - 1
     n_ad = args.steps * sch_d["sweeps"] * M1
     n_r = args.steps * sch_d["sweeps"] * M1 * r if r else n_ad
-    model = work_model(ns, sch_d["n_coarse"], r)
+    model = work_model(ns, mech["nr"], sch_d["n_coarse"], r)
     dominant = max(kern, key=lambda k: kern[k][0])
     dur_ms = kern[dominant][0] / kern[dominant][1]
     if dominant in model:

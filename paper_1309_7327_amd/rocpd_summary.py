@@ -28,7 +28,8 @@ _KINDS = [
     (r"k_prim_to_cons<", "prim_to_cons"), (r"k_ghost<", "ghost"), (r"k_prims<", "prims"),
     (r"k_vgrad<", "vgrad"), (r"k_dir<\d+, 0", "dir_x"), (r"k_dir<\d+, 1", "dir_y"), (r"k_dir<\d+, 2", "dir_z"),
     (r"k_chem<", "chem"), (r"k_sdc_node<", "sdc_node"), (r"k_mr_step<", "mr_fine"), (r"k_mr_src<", "mr_src"),
-    (r"k_dir_adj<\d+, 0", "dir_adj_x"), (r"k_dir_adj<\d+, 1", "dir_adj_y"), (r"k_dir_adj<\d+, 2", "dir_adj_z"),
+    (r"k_adj_(coef|g1|g2|g3)<\d+, 0", "dir_adj_x"), (r"k_adj_(coef|g1|g2|g3)<\d+, 1", "dir_adj_y"),
+    (r"k_adj_(coef|g1|g2|g3)<\d+, 2", "dir_adj_z"),
     (r"k_chem_adj<", "chem_adj"), (r"k_vgrad_adj<", "vgrad_adj"), (r"k_prims_adj<", "prims_adj"),
     (r"k_fold<", "fold"), (r"k_(fill0|axpy_multi|lincomb|lnA_reduce)\b", "adj_linalg"),
 ]
@@ -87,13 +88,15 @@ def traffic(fetch_db, write_db, workload, out_dir, cmd_fetch, cmd_write):
     copy_w = max(v for k, vs in w.items() if "copyBuffer" in k for v in vs)
     ff = CALIB_BYTES / (copy_f * 1024.0)
     fw = CALIB_BYTES / (copy_w * 1024.0)
-    by_kind = collections.defaultdict(lambda: [[], []])
+    # a kind may span several kernels (the direction adjoint launches four
+    # per call): its bytes per call are the sum of their per-launch means
+    by_kind = collections.defaultdict(lambda: collections.defaultdict(lambda: [[], []]))
     for k, vs in f.items():
         if kind_of(k):
-            by_kind[kind_of(k)][0].extend(vs)
+            by_kind[kind_of(k)][short_name(k)][0].extend(vs)
     for k, vs in w.items():
         if kind_of(k):
-            by_kind[kind_of(k)][1].extend(vs)
+            by_kind[kind_of(k)][short_name(k)][1].extend(vs)
     h = source_hash()
     lines = [f"# HBM traffic per launch: {workload}", "",
              "Commands (repository root on the GPU box; `cd /tmp && export TMPDIR=/tmp` first):", "",
@@ -106,17 +109,19 @@ def traffic(fetch_db, write_db, workload, out_dir, cmd_fetch, cmd_write):
              "| kernel | launches | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | HBM bytes per launch |",
              "|---|---:|---:|---:|---:|"]
     for kind in sorted(by_kind):
-        fv, wv = by_kind[kind]
-        if not fv or not wv:
+        ks = by_kind[kind]
+        if any(not fv or not wv for fv, wv in ks.values()):
             continue
-        mf, mw = sum(fv) / len(fv), sum(wv) / len(wv)
+        mf = sum(sum(fv) / len(fv) for fv, _ in ks.values())
+        mw = sum(sum(wv) / len(wv) for _, wv in ks.values())
+        n = max(len(fv) for fv, _ in ks.values())
         b = mf * 1024.0 * ff + mw * 1024.0 * fw
-        rec = {"kernel": kind, "workload": workload, "launches": len(fv), "fetch_kib_raw": mf,
+        rec = {"kernel": kind, "workload": workload, "kernels": sorted(ks), "launches": n, "fetch_kib_raw": mf,
                "write_kib_raw": mw, "fetch_factor": ff, "write_factor": fw, "bytes_per_launch": b,
                "source_hash": h, "commands": [cmd_fetch, cmd_write]}
         with open(os.path.join(out_dir, f"traffic_{kind}_{workload}.json"), "w") as fh:
             json.dump(rec, fh, indent=1)
-        lines.append(f"| {kind} | {len(fv)} | {mf:.4g} | {mw:.4g} | {b:.4g} |")
+        lines.append(f"| {kind} | {n} | {mf:.4g} | {mw:.4g} | {b:.4g} |")
     with open(os.path.join(out_dir, f"traffic_{workload}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
