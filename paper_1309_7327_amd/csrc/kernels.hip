@@ -125,10 +125,13 @@ __global__ __launch_bounds__(256) void k_ghost(const BoxDev *__restrict__ boxes,
   }
 }
 
-// out_mode: 0 leave the right-hand side alone, 1 zero it, 2 chemistry source.
+// out_mode: 0 leave the right-hand side alone, 1 zero it, 2 chemistry source
+// (only the CHEM instance takes mode 2: without the chemistry the kernel
+// needs fewer registers: 164 instead of 218 at 9 species, three waves per
+// SIMD instead of two).
 // warm != 0: start the Newton solve from the temperature the previous
 // evaluation left in P (when it lies in the fit range), else from 1000 K.
-template <int NS>
+template <int NS, bool CHEM>
 __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
                                                TileShape ts, FRef Uref, double *__restrict__ Pbase,
@@ -136,8 +139,9 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
                                                const DevMech *__restrict__ m, int *err) {
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
-  NSDC_CHEM_LDS(NS, 65536, chem_sh);
-  double *sh = chem_sh + (chem_in_lds<NS, 65536>() ? threadIdx.x : 0);
+  constexpr int LIM = CHEM ? 65536 : 0;
+  NSDC_CHEM_LDS(NS, LIM, chem_sh);
+  double *sh = chem_sh + (chem_in_lds<NS, LIM>() ? threadIdx.x : 0);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -192,9 +196,9 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
     double *F = Fout.get(w.box, b.offI * NU);
 #pragma unroll
     for (int q = 0; q < 5; ++q) F[q * nI + i] = 0.0;
-    if (out_mode == 2) {
+    if (CHEM && out_mode == 2) {
       double wd[NS];
-      production_any<NS, 65536>(m, rho, T, Y, wd, sh);
+      production_any<NS, LIM>(m, rho, T, Y, wd, sh);
 #pragma unroll
       for (int k = 0; k < NS; ++k) F[(5 + k) * nI + i] = wd[k];
     } else {
@@ -737,8 +741,13 @@ struct Launch {
   }
   static void prims(const LaunchCtx &c, FRef U, double *P, FRef F, int out_mode, int warm) {
     prof_begin(c.prof, K_PRIMS, c.stream);
-    hipLaunchKernelGGL(k_prims<NS>, dim3(grid_for(c.nS, c.cap)), dim3(c.tsS.tx * c.tsS.ty * c.tsS.tz), 0,
-                       c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F, out_mode, warm, c.mech, c.err);
+    const dim3 grid(grid_for(c.nS, c.cap)), block(c.tsS.tx * c.tsS.ty * c.tsS.tz);
+    if (out_mode == 2)
+      hipLaunchKernelGGL((k_prims<NS, true>), grid, block, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F,
+                         out_mode, warm, c.mech, c.err);
+    else
+      hipLaunchKernelGGL((k_prims<NS, false>), grid, block, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F,
+                         out_mode, warm, c.mech, c.err);
     prof_end(c.prof, K_PRIMS, c.stream);
   }
   static void vgrad(const LaunchCtx &c, const double *P, double *G) {
