@@ -732,6 +732,7 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
     for (int i = 0; i < 4; ++i) d.sc[k][i] = a[i + 1] / (i + 1);
     d.s7[k] = a[6];
   }
+  for (int j = 0; j < 64; ++j) d.e2tab[j] = (double)exp2l((long double)j / 64.0L);
   for (int j = 0; j < m->nr; ++j) {
     if (!(m->A[j] > 0)) return fail(c, SDC_EINVAL, "pre-exponential must be > 0");
     d.lnA[j] = std::log(m->A[j]);

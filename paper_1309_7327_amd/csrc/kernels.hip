@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
   constexpr int NU = L::NU, NP = L::NP;
   constexpr int LIM = CHEM ? 65536 : 0;
   NSDC_CHEM_LDS(NS, LIM, chem_sh);
-  double *sh = chem_sh + (chem_in_lds<NS, LIM>() ? threadIdx.x : 0);
+  double *sh = chem_lds_setup<NS, LIM>(chem_sh, m);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_chem(const BoxDev *__restrict__ boxes,
                                               const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
   NSDC_CHEM_LDS(NS, NSDC_CHEM_LDS_LIMIT, chem_sh);
-  double *sh = chem_sh + (chem_in_lds<NS, NSDC_CHEM_LDS_LIMIT>() ? threadIdx.x : 0);
+  double *sh = chem_lds_setup<NS, NSDC_CHEM_LDS_LIMIT>(chem_sh, m);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
                                                  const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
   NSDC_CHEM_LDS(NS, NSDC_CHEM_LDS_LIMIT, chem_sh);
-  double *sh = chem_sh + (chem_in_lds<NS, NSDC_CHEM_LDS_LIMIT>() ? threadIdx.x : 0);
+  double *sh = chem_lds_setup<NS, NSDC_CHEM_LDS_LIMIT>(chem_sh, m);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];

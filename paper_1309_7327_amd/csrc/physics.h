@@ -12,6 +12,31 @@ namespace nsdc {
 constexpr double RU = 8.31446261815324;
 constexpr double PREF = 101325.0;
 constexpr double LN_RU_PREF = -9.408091968943316;  // ln(RU / PREF)
+
+// e^x for the reaction rates: x = k ln2/64 + r with k = rint(64 x / ln 2) and
+// |r| <= ln2/128 (Cody-Waite reduction with a two-part ln2/64 whose leading
+// part has 37 significant bits, so k times it is exact for |k| < 2^16), e^r
+// by its Taylor polynomial to degree 5 (truncation below 4e-17 relative),
+// 2^(j/64), j = k mod 64, from the table tab (correctly rounded entries) and
+// 2^floor(k/64) by ldexp (which also gives the overflow and underflow
+// limits).  Error within about one ulp.
+constexpr double EXP_INV_LN2_64 = 92.33248261689366;        // 64 / ln 2
+constexpr double EXP_LN2_64_HI = 0.010830424696223417;      // 0x3f862e42fefa0000
+constexpr double EXP_LN2_64_LO = 2.572804622327669e-14;     // ln2/64 - HI
+__device__ __forceinline__ double exp_tab(double x, const double *tab) {
+  const double kd = rint(x * EXP_INV_LN2_64);
+  const int k = (int)kd;
+  double r = fma(-kd, EXP_LN2_64_HI, x);
+  r = fma(-kd, EXP_LN2_64_LO, r);
+  // e^r - 1 = r (1 + r/2 + r^2/6 + r^3/24 + r^4/120), added to the table
+  // entry t as t + t (e^r - 1) so only the last rounding falls on the result
+  double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  p = fma(r, p, 1.0 / 6.0);
+  p = fma(r, p, 0.5);
+  p = fma(r, p, 1.0);
+  const double t = tab[k & 63];
+  return ldexp(fma(t, r * p, t), k >> 6);
+}
 // eighth-order centred first-derivative weights
 constexpr double C1 = 4.0 / 5.0, C2 = -1.0 / 5.0, C3 = 4.0 / 105.0, C4 = -1.0 / 280.0;
 
@@ -123,15 +148,17 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
 // The same source with the per-cell arrays c, g and w in this thread's LDS
 // column: entry k of array a at sh[(a (NS+1) + k) 256] (consecutive threads
 // own consecutive doubles).  A species index then costs one address add
-// shared by the three arrays, instead of indexed register moves; every
-// operation and its order is the same as in production().
+// shared by the three arrays, instead of indexed register moves.  The
+// exponentials use exp_tab with the workgroup's copy of the 2^(j/64) table
+// (64 doubles after the three arrays); every other operation and its order
+// is the same as in production().
 template <int NS, int LIMIT = 65536>
 constexpr bool chem_in_lds() {
-  return 3 * (NS + 1) * 256 * sizeof(double) <= LIMIT;
+  return (3 * (NS + 1) * 256 + 64) * sizeof(double) <= LIMIT;
 }
 template <int NS>
 __device__ void production_sh(const DevMech *__restrict__ m, double rho, double T, const double *Y,
-                              double *wdot, double *sh) {
+                              double *wdot, double *sh, const double *tab) {
   constexpr int S = 256, A = (NS + 1) * S;
   const double lnT = log(T), invT = 1.0 / T;
   asm volatile("" ::: "memory");
@@ -151,8 +178,8 @@ __device__ void production_sh(const DevMech *__restrict__ m, double rho, double 
     const int r0 = m->rs[j][0] * S, r1 = m->rs[j][1] * S, p0 = m->ps[j][0] * S, p1 = m->ps[j][1] * S;
     const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
     const double dg = (sh[A + p0] + sh[A + p1]) - (sh[A + r0] + sh[A + r1]);
-    const double kf = exp(lnkf);
-    const double kr = exp(lnkf + dg + m->dnu[j] * lnRTp);
+    const double kf = exp_tab(lnkf, tab);
+    const double kr = exp_tab(lnkf + dg + m->dnu[j] * lnRTp, tab);
     const double q = kf * sh[r0] * sh[r1] - kr * sh[p0] * sh[p1];
     atomicAdd(sh + 2 * A + r0, -q);
     atomicAdd(sh + 2 * A + r1, -q);
@@ -164,18 +191,32 @@ __device__ void production_sh(const DevMech *__restrict__ m, double rho, double 
 }
 
 // Chemistry source through the LDS column when the block's arrays fit in
-// LIMIT bytes (sh: this thread's column of a [3][NS+1][256] shared array),
-// else in registers.
+// LIMIT bytes (sh: this thread's column of a [3][NS+1][256] shared array
+// followed by the 2^(j/64) table, from chem_lds_setup), else in registers.
 template <int NS, int LIMIT = 65536>
 __device__ __forceinline__ void production_any(const DevMech *__restrict__ m, double rho, double T,
                                                const double *Y, double *wdot, double *sh) {
   if constexpr (chem_in_lds<NS, LIMIT>())
-    production_sh<NS>(m, rho, T, Y, wdot, sh);
+    production_sh<NS>(m, rho, T, Y, wdot, sh, sh - threadIdx.x + 3 * (NS + 1) * 256);
   else
     production<NS>(m, rho, T, Y, wdot);
 }
 #define NSDC_CHEM_LDS(NS, LIMIT, name) \
-  __shared__ double name[chem_in_lds<NS, LIMIT>() ? 3 * ((NS) + 1) * 256 : 1]
+  __shared__ double name[chem_in_lds<NS, LIMIT>() ? 3 * ((NS) + 1) * 256 + 64 : 1]
+// This thread's chemistry column in the LDS array `base` (NSDC_CHEM_LDS),
+// once the workgroup has copied the 2^(j/64) table behind the three arrays.
+// Every thread of the workgroup must call it, before any work-item loop.
+template <int NS, int LIMIT>
+__device__ __forceinline__ double *chem_lds_setup(double *base, const DevMech *__restrict__ m) {
+  if constexpr (chem_in_lds<NS, LIMIT>()) {
+    double *tab = base + 3 * (NS + 1) * 256;
+    for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = m->e2tab[j];
+    __syncthreads();
+    return base + threadIdx.x;
+  } else {
+    return base;
+  }
+}
 
 // Conserved state of one cell -> density, velocity, mass fractions and
 // temperature.  Returns an error bit mask (0 = ok).
