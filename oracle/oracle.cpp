@@ -8,8 +8,7 @@
 // for the flux-difference form and the face sum H with the 8x8 matrix M),
 // Section 2.4 (chain rule for the correction-velocity terms).  Readings where
 // the paper is silent (thermodynamic fits, rate law, transport model, form
-// of the mixed viscous terms) are the ones listed in the design notes and are
-// restated at each function.
+// of the mixed viscous terms) are restated at each function.
 //
 // The right-hand side is evaluated one output cell at a time from primitive
 // fields stored on the 4-layer periodic ghost grid; every derivative is taken

@@ -99,7 +99,7 @@ def traffic(fetch_db, write_db, workload, out_dir, cmd_fetch, cmd_write):
             by_kind[kind_of(k)][short_name(k)][1].extend(vs)
     h = source_hash()
     lines = [f"# HBM traffic per launch: {workload}", "",
-             "Commands (repository root on the GPU box; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "Commands (from the repository root; `cd /tmp && export TMPDIR=/tmp` before rocprofv3):", "",
              "```", cmd_fetch, cmd_write,
              f"python -m paper_1309_7327_amd.rocpd_summary traffic --fetch <fetch db> --write <write db> "
              f"--workload {workload} --out-dir profiles", "```", "",
@@ -144,7 +144,7 @@ def main():
     if a.cmd == "kernels":
         print(f"# {a.title}\n")
         if a.command:
-            print("Command (repository root on the GPU box):\n\n```\n" + a.command + "\n```\n")
+            print("Command (from the repository root):\n\n```\n" + a.command + "\n```\n")
         print(f"Kernel sources hash {source_hash()}.\n")
         print("| kernel | calls | total ns | average ns | % |\n|---|---:|---:|---:|---:|")
         for name, n, tot, avg, pct in kernel_table(a.db):

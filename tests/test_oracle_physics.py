@@ -1,6 +1,6 @@
 """Pins of the oracle's thermochemistry and right-hand side against
 identities, invariants and a spectral evaluation of the continuous operators
-(Section 2.1 and the readings listed in the design notes)."""
+(Section 2.1 and the readings restated in the oracle)."""
 import numpy as np
 import pytest
 
