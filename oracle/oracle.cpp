@@ -118,13 +118,14 @@ struct Mech {
   std::vector<double> W, nasa, A, b, Ea, Le;
   std::vector<int> nuf, nur;
   double Tlo, Thi, mu_ref, T_ref, mu_exp, Pr, bulk;
+  int ref;   // -1 correction velocity, else the reference species
   double M[8][8];
   explicit Mech(const omech *m)
       : ns(m->ns), nr(m->nr), W(m->W, m->W + m->ns), nasa(m->nasa, m->nasa + 7 * m->ns),
         A(m->A, m->A + m->nr), b(m->b, m->b + m->nr), Ea(m->Ea, m->Ea + m->nr),
         Le(m->Le, m->Le + m->ns), nuf(m->nu_f, m->nu_f + m->nr * m->ns),
         nur(m->nu_r, m->nu_r + m->nr * m->ns), Tlo(m->Tlo), Thi(m->Thi), mu_ref(m->mu_ref),
-        T_ref(m->T_ref), mu_exp(m->mu_exp), Pr(m->Pr), bulk(m->bulk_ratio) {
+        T_ref(m->T_ref), mu_exp(m->mu_exp), Pr(m->Pr), bulk(m->bulk_ratio), ref(m->ref_species) {
     narrow8(m->m47, m->m48, M);
   }
 };
@@ -424,6 +425,49 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
         f[s + 4] = g.mu[c] * t1 + (g.xi[c] - 2.0 / 3.0 * g.mu[c]) * g.u[d][c] * divt;
       }
       out[4] = out[4] + d1(f, h);
+      if (m.ref >= 0) {
+        // reference species (Section 2.1): species k != ref carry the mixture
+        // model flux Fbar_k, the reference species carries -sum of them, and
+        // the energy flux sum_k F_k h_k becomes sum_{k != ref} Fbar_k (h_k -
+        // h_ref) (Section 2.4), so the pairs are (rho D_k (h_k - h_ref), X_k)
+        // and (rho D_k (h_k - h_ref)(X_k - Y_k)/p, p); no correction velocity
+        const int kr = m.ref;
+        for (int ks = 0; ks < ns; ++ks) {
+          if (ks == kr) continue;
+          for (int s = -4; s <= 4; ++s) {
+            long c = pt(d, s);
+            a[s + 4] = g.rhoD[ks * n + c];
+            uu[s + 4] = g.X[ks * n + c];
+          }
+          S Lx = narrow(a, uu, h, m.M);
+          for (int s = -4; s <= 4; ++s) {
+            long c = pt(d, s);
+            a[s + 4] = g.rhoD[ks * n + c] * (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
+            uu[s + 4] = g.p[c];
+          }
+          S Lp = narrow(a, uu, h, m.M);
+          out[5 + ks] = out[5 + ks] + Lx + Lp;
+          out[5 + kr] = out[5 + kr] - (Lx + Lp);
+          for (int s = -4; s <= 4; ++s) {
+            long c = pt(d, s);
+            a[s + 4] = g.rhoD[ks * n + c] * (g.h[ks * n + c] - g.h[kr * n + c]);
+            uu[s + 4] = g.X[ks * n + c];
+          }
+          out[4] = out[4] + narrow(a, uu, h, m.M);
+        }
+        for (int s = -4; s <= 4; ++s) {
+          long c = pt(d, s);
+          S sum = 0.0;
+          for (int ks = 0; ks < ns; ++ks)
+            if (ks != kr)
+              sum = sum + g.rhoD[ks * n + c] * (g.h[ks * n + c] - g.h[kr * n + c]) *
+                              (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
+          a[s + 4] = sum;
+          uu[s + 4] = g.p[c];
+        }
+        out[4] = out[4] + narrow(a, uu, h, m.M);
+        continue;
+      }
       // species diffusion
       for (int ks = 0; ks < ns; ++ks) {
         for (int s = -4; s <= 4; ++s) {
@@ -474,7 +518,7 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
       }
       Vc[d] = vc;
     }
-    for (int ks = 0; ks < ns; ++ks) {
+    for (int ks = 0; ks < ns && m.ref < 0; ++ks) {
       S t = g.Y[ks * n + c0] * divVc;
       for (int d = 0; d < 3; ++d) t = t + Vc[d] * DY[d * ns + ks];
       out[5 + ks] = out[5 + ks] + t;

@@ -28,6 +28,10 @@ typedef struct {
   const double *Le;         /* [ns] Lewis numbers */
   double mu_ref, T_ref, mu_exp, Pr, bulk_ratio;
   double m47, m48;
+  /* species diffusion consistent with mass conservation (Section 2.1): -1
+     correction velocity; k >= 0 reference species k, whose flux is minus the
+     sum of the others' mixture-model fluxes */
+  int ref_species;
 } omech;
 
 enum { ORC_HYP = 1, ORC_DIFF = 2, ORC_REACT = 4 };

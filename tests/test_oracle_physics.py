@@ -273,3 +273,53 @@ def test_diffusive_fluxes_converge_to_continuous_divergence(orc, mechs):
         errs.append(max(e))
     assert errs[-1] < 1e-6
     assert _rates(errs)[0] > 7.0, errs
+
+
+@pytest.mark.parametrize("kind,ref", [("mech9le", 8), ("mech9le", 0)])
+def test_reference_species_fluxes_converge_to_continuous_divergence(orc, mechs, kind, ref):
+    """Reference-species form (Section 2.1): F_k = Fbar_k for k != ref, F_ref =
+    -sum of the others; the energy flux is sum_k F_k h_k.  Eighth-order
+    convergence to the spectral divergence of those fluxes, and species
+    diffusion terms that sum to zero."""
+    om0 = mechs[kind]
+    om = orc.Mechanism(om0.mech, ref_species=ref)
+    m = om.mech
+    W = m["W"]
+    errs = []
+    for n in (16, 32):
+        prim, dx = _smooth_fields(n, om, varying_T=True)
+        U = orc.prim_to_cons(om, prim)
+        f = orc.rhs(om, U, dx, parts=orc.DIFF)
+        T, Y, p = prim["T"], prim["Y"], prim["p"]
+        flatT = T.reshape(-1)
+        cpR = np.zeros((om.ns, flatT.size))
+        hRT = np.zeros_like(cpR)
+        for c, Tc in enumerate(flatT):
+            cpR[:, c], hRT[:, c], _ = orc.species_thermo(om, Tc)
+        cpR = cpR.reshape((om.ns,) + T.shape)
+        hRT = hRT.reshape((om.ns,) + T.shape)
+        Wbar = 1.0 / np.sum(Y / W[:, None, None, None], axis=0)
+        X = Y * Wbar / W[:, None, None, None]
+        h = RU / W[:, None, None, None] * T * hRT
+        cp = np.sum(Y * RU / W[:, None, None, None] * cpR, axis=0)
+        mu = m["mu_ref"] * (T / m["T_ref"]) ** m["mu_exp"]
+        lam = mu * cp / m["Pr"]
+        rhoD = lam / cp / m["Le"][:, None, None, None]
+        gp = _grad(p, dx)
+        Fbar = [[-rhoD[k] * (gX + (X[k] - Y[k]) * gpd / p) for gX, gpd in zip(_grad(X[k], dx), gp)]
+                for k in range(om.ns)]
+        F = [Fbar[k] if k != ref else [-sum(Fbar[j][d] for j in range(om.ns) if j != ref) for d in range(3)]
+             for k in range(om.ns)]
+        species = [-_div(F[k], dx) for k in range(om.ns)]
+        gT = _grad(T, dx)
+        energy = _div([lam * gT[d] - sum(F[k][d] * h[k] for k in range(om.ns)) for d in range(3)], dx)
+        e = [np.abs(f[5 + k] - species[k]).max() / np.abs(species[k]).max() for k in range(om.ns)]
+        e.append(np.abs(f[4] - energy).max() / np.abs(energy).max())
+        errs.append(max(e))
+        tot = np.sum(f[5:], axis=0)
+        assert np.abs(tot).max() <= 1e-12 * np.abs(f[5:]).max()
+    assert errs[-1] < 1e-6
+    assert _rates(errs)[0] > 7.0, errs
+    # the two forms differ (the correction velocity is not zero here)
+    f0 = orc.rhs(om0, U, dx, parts=orc.DIFF)
+    assert np.abs(f0[5 + ref] - f[5 + ref]).max() > 1e-3 * np.abs(f[5 + ref]).max()
