@@ -177,6 +177,17 @@ int rhs_vjp(sdc_context *ctx, const box_desc *box, double *U, const double *dUdt
  * pre-exponential factors at values of their choice. */
 int set_log_prefactors(sdc_context *ctx, const double *lnA);
 
+/* Species diffusion consistent with mass conservation (Section 2.1).
+ * k = -1 (the default after set_mechanism): correction velocity V_c, the
+ * chain-rule form of Section 2.4.  k in [0, ns): reference species k, e.g.
+ * N2: species j != k carry the mixture-model flux Fbar_j, species k carries
+ * -sum_{j != k} Fbar_j, and the energy flux is sum_{j != k} Fbar_j (h_j -
+ * h_k) (Section 2.4); no correction velocity.  Synchronous (waits for the
+ * device before updating its copy of the mechanism).  Errors: SDC_ENOMECH
+ * without a mechanism, SDC_EINVAL for k outside [-1, ns).  rhs_vjp and
+ * sdc_step_vjp return SDC_EINVAL while a reference species is set. */
+int set_reference_species(sdc_context *ctx, int k);
+
 /* Bytes of device workspace sdc_step_vjp needs for nsteps steps. */
 int sdc_vjp_workspace_size(const sdc_context *ctx, const box_desc *box, const sdc_scheme *scheme,
                            int nsteps, size_t *bytes);

@@ -405,6 +405,7 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.tsS = p->tsS;
   l.cap = c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : 1 << 30);
   l.mech = c->d_mech;
+  l.ref_species = c->h_mech.ref;
   l.err = c->d_err;
   l.prof = c->prof.get();
   l.smc_stencil = c->smc_stencil;
@@ -782,6 +783,8 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
   for (int o = 0; o < 9; ++o)
     for (int col = 0; col < 9; ++col)
       d.B[o][col] = ((o >= 1 && col >= 1) ? d.M[o - 1][col - 1] : 0.0) - ((o <= 7 && col <= 7) ? d.M[o][col] : 0.0);
+  // a new mechanism starts in the correction-velocity form
+  d.ref = -1;
   HIPCHECK(c, hipSetDevice(c->device));
   HIPCHECK(c, hipMemcpy(c->d_mech, &d, sizeof d, hipMemcpyHostToDevice));
   c->ops = o;
@@ -1185,6 +1188,8 @@ SdcVjpLayout sdc_vjp_layout(const Plan *p, int ns, int nr, int cap, const sdc_sc
 int check_vjp_args(sdc_context *c, const box_desc *box) {
   if (!c) return SDC_EINVAL;
   if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  if (c->h_mech.ref >= 0)
+    return fail(c, SDC_EINVAL, "the adjoint covers the correction-velocity form of the species diffusion only");
   int rc = check_box(c, box);
   if (rc) return rc;
   const TileShape t = c->forceI;
@@ -1373,6 +1378,17 @@ int set_log_prefactors(sdc_context *c, const double *lnA) {
     if (!std::isfinite(lnA[j])) return fail(c, SDC_EINVAL, "ln A must be finite");
     c->h_mech.lnA[j] = lnA[j];
   }
+  HIPCHECK(c, hipSetDevice(c->device));
+  HIPCHECK(c, hipDeviceSynchronize());
+  HIPCHECK(c, hipMemcpy(c->d_mech, &c->h_mech, sizeof(DevMech), hipMemcpyHostToDevice));
+  return SDC_OK;
+}
+
+int set_reference_species(sdc_context *c, int k) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  if (k < -1 || k >= c->h_mech.ns) return fail(c, SDC_EINVAL, "reference species out of range");
+  c->h_mech.ref = k;
   HIPCHECK(c, hipSetDevice(c->device));
   HIPCHECK(c, hipDeviceSynchronize());
   HIPCHECK(c, hipMemcpy(c->d_mech, &c->h_mech, sizeof(DevMech), hipMemcpyHostToDevice));

@@ -246,7 +246,9 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
 
 // Occupancy: three workgroups per CU along x for up to 9 species (a small
 // spill), two otherwise (larger spills cost more than the extra waves gain).
-template <int NS, int D, bool FIXED>
+// REF: the reference-species form of the species diffusion (its own
+// instance: the branch would otherwise raise the register use of both).
+template <int NS, int D, bool FIXED, bool REF>
 __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
                                              TileShape ts, FRef Uref,
@@ -401,7 +403,53 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const Bo
         const double Dpp = d1(pp, idx) / pp[4];
         const double rd4 = rd[4];
         double divVc = 0.0, Vc = 0.0;
-        if constexpr (SPEC_LDS) {
+        if constexpr (REF) {
+          const int ref = m->ref;
+          // reference species (Section 2.1): species k != ref take their
+          // mixture-model flux terms, the reference species minus their sum;
+          // the energy pairs carry h_k - h_ref (Section 2.4); no V_c terms
+          double tsum = 0.0;
+#pragma unroll 1
+          for (int k = 0; k < NS; ++k) {
+            if (HYP_IN_SPECIES && (parts & 1)) {
+              line(U + (5 + k) * nS, u9);
+              spc(k) -= d1p(u9, ud, idx);
+            }
+            if (k == ref) continue;
+            const double iLe = m->invLe[k];
+            line(P + (L::PX + k) * nS, u9);
+            bvec<FIXED>(m, u9, v);
+            line(P + (L::PY + k) * nS, g);
+#pragma unroll
+            for (int o = 0; o < 9; ++o) u9[o] -= g[o];
+            const double Lp = dot9(u9, wp);
+            const double Lx = dot9(rd, v);
+            line(P + (L::PH + k) * nS, g);
+            {
+              double hr[9];
+              line(P + (L::PH + ref) * nS, hr);
+#pragma unroll
+              for (int o = 0; o < 9; ++o) g[o] -= hr[o];
+            }
+            double LhX = 0.0, Lpe = 0.0;
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+              LhX += rd[o] * g[o] * v[o];
+              Lpe += u9[o] * g[o] * wp[o];
+            }
+            const double t = iLe * (Lx + Lp) * idx2;
+            spc(k) += t;
+            tsum += t;
+            acc[4] += iLe * (LhX + Lpe) * idx2;
+          }
+          if constexpr (ACC_LDS) {
+            spc(ref) -= tsum;
+          } else {
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+              if (k == ref) spc(k) -= tsum;
+          }
+        } else if constexpr (SPEC_LDS) {
           // one pass over the species lines: the centre values Y_k and first
           // derivatives D_D Y_k of the final Y_k div V_c + V_c D_D Y_k terms
           // wait in this thread's LDS column; the energy counterpart is
@@ -762,15 +810,27 @@ struct Launch {
     const TileShape ts = c.tsD[d];
     const dim3 grid(grid_for(c.nD[d], c.cap)), block(ts.tx * ts.ty * ts.tz);
     prof_begin(c.prof, K_DIR_X + d, c.stream);
-    if (d == 0)
-      hipLaunchKernelGGL((k_dir<NS, 0, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nD[0], ts, U, P,
-                         G, F, parts, c.mech);
-    else if (d == 1)
-      hipLaunchKernelGGL((k_dir<NS, 1, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nD[1], ts, U, P,
-                         G, F, parts, c.mech);
-    else
-      hipLaunchKernelGGL((k_dir<NS, 2, FIXED>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nD[2], ts, U, P,
-                         G, F, parts, c.mech);
+    if (c.ref_species >= 0) {
+      if (d == 0)
+        hipLaunchKernelGGL((k_dir<NS, 0, FIXED, true>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nD[0], ts,
+                           U, P, G, F, parts, c.mech);
+      else if (d == 1)
+        hipLaunchKernelGGL((k_dir<NS, 1, FIXED, true>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nD[1], ts,
+                           U, P, G, F, parts, c.mech);
+      else
+        hipLaunchKernelGGL((k_dir<NS, 2, FIXED, true>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nD[2], ts,
+                           U, P, G, F, parts, c.mech);
+    } else {
+      if (d == 0)
+        hipLaunchKernelGGL((k_dir<NS, 0, FIXED, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nD[0], ts,
+                           U, P, G, F, parts, c.mech);
+      else if (d == 1)
+        hipLaunchKernelGGL((k_dir<NS, 1, FIXED, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nD[1], ts,
+                           U, P, G, F, parts, c.mech);
+      else
+        hipLaunchKernelGGL((k_dir<NS, 2, FIXED, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nD[2], ts,
+                           U, P, G, F, parts, c.mech);
+    }
     prof_end(c.prof, K_DIR_X + d, c.stream);
   }
   static void dir(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F,

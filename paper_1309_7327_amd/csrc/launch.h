@@ -38,6 +38,7 @@ struct LaunchCtx {
   int *err;
   Profiler *prof;
   bool smc_stencil;   // the default narrow-stencil parameters: compile-time B
+  int ref_species;    // species diffusion: -1 correction velocity, else the reference species
 };
 
 struct Ops {

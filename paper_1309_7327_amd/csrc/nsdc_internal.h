@@ -34,6 +34,7 @@ struct DevMech {
   double M[8][8];             // narrow-stencil matrix, [m+3][n+3]
   double B[9][9];             // face-difference matrix B_oc = M_{o-1,c-1} - M_{o,c}
   double e2tab[64];           // 2^(j/64), j = 0..63 (correctly rounded), for the rate exponentials
+  int ref;                    // species diffusion: -1 correction velocity, k >= 0 reference species k
 };
 
 // One box of a batch.  offS / offI: offsets (in cells) of this box inside

@@ -64,6 +64,7 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_int)],
     "rhs_vjp": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
     "set_log_prefactors": [_vp, _vp],
+    "set_reference_species": [_vp, _ip],
     "sdc_vjp_workspace_size": [_vp, ctypes.POINTER(BoxDesc), ctypes.POINTER(Scheme), _ip,
                                ctypes.POINTER(ctypes.c_size_t)],
     "sdc_step_vjp": [_vp, ctypes.POINTER(BoxDesc), _vp, _d, _ip, ctypes.POINTER(Scheme), _vp, _vp, _vp,
@@ -203,6 +204,11 @@ class Context:
         """U_bar += (d rhs/dU)^T dUdt_bar; lnA_bar += (d rhs/d lnA)^T dUdt_bar."""
         self._check(_lib.rhs_vjp(self.h, ctypes.byref(bx), _ptr(U), _ptr(dUdt_bar), _ptr(U_bar),
                                  _ptr(lnA_bar), parts, _stream(stream)))
+
+    def set_reference_species(self, k=-1):
+        """-1: correction-velocity species diffusion (default); k >= 0:
+        reference species k (Section 2.1)."""
+        self._check(_lib.set_reference_species(self.h, int(k)))
 
     def set_log_prefactors(self, lnA):
         a = np.ascontiguousarray(lnA, dtype=np.float64)

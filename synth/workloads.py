@@ -7,6 +7,9 @@
                   4 Gauss-Lobatto nodes, chemistry on 5 Gauss-Lobatto nodes in
                   each coarse interval (4 sub-steps per fluid node), 6 sweeps.
   box256_mrsdc    256^3, 21 species / 84 reactions, 5 multirate steps.
+  box128_mrsdc_n2ref  box128_mrsdc's flame and scheme with the non-unity
+                  Lewis number variant of the 9-species mechanism and N2 as
+                  the reference species of the species diffusion.
   batch240_sdc    240 independent boxes with edges drawn from {16..48},
                   9/21, single-rate SDC as box16_sdc.
   box64_adjoint   64^3, 9/21, vector-Jacobian product of the right-hand side.
@@ -29,6 +32,9 @@ WORKLOADS = {
                       scheme=dict(kind="sdc", n_coarse=4, sweeps=6, n_fine=0), steps=1),
     "box128_mrsdc": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9", recipe="turb", seed=2, kmax=16,
                          scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=10),
+    "box128_mrsdc_n2ref": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9le", recipe="turb", seed=2, kmax=16,
+                               scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=10,
+                               ref_species=8),
     "box256_mrsdc": dict(shape=(256, 256, 256), dx=1e-4, mech="mech21", recipe="turb", seed=3, kmax=32,
                          scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=5),
     "batch240_sdc": dict(nbox=240, dx=1e-4, mech="mech9", recipe="sines", seed=1000,
