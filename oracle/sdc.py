@@ -99,13 +99,33 @@ class Counter:
         return self.f(U, t)
 
 
-def sdc_run(f, U0, t0, dt, nodes, K, nsteps, perturb=None):
+def sdc_residual(U0, F, UM, q, dt):
+    """Size of the SDC residual R = U_0 + dt q.F - U_M (eq. residual), q the
+    last row of the integration matrix: the largest over state components of
+    max|R_c| / max|U_0,c| (the paper leaves the norm open; this reading makes
+    it independent of each component's units)."""
+    R = U0 + dt * sum(qj * Fj for qj, Fj in zip(q, F)) - UM
+    nc = R.shape[0]
+    r = np.abs(R).reshape(nc, -1).max(axis=1)
+    u = np.abs(U0).reshape(nc, -1).max(axis=1)
+    return float(max(r[c] / u[c] for c in range(nc) if u[c] > 0))
+
+
+def sdc_run(f, U0, t0, dt, nodes, K, nsteps, perturb=None, residual_ratio=0.0, history=None):
     """Single-rate SDC: nsteps steps of K sweeps each (eq. expsdc).
     f(U, t) -> dU/dt.  Returns the final state.  perturb (optional) is
-    applied to every new node state (used to measure rounding sensitivity)."""
+    applied to every new node state (used to measure rounding sensitivity).
+
+    residual_ratio > 1: after every sweep but a step's last the residual of
+    eq. (residual) is measured, and the step's remaining sweeps are skipped
+    once |R^{k-1}| / |R^k| < residual_ratio (the sweeps have stopped
+    improving the collocation residual).  history (a list, optional)
+    receives (step, sweep, |R|) of every measurement and ("sweeps", n) per
+    step."""
     perturb = perturb or (lambda U: U)
     M = len(nodes) - 1
     S = s_matrix(nodes)
+    q = S.sum(axis=0)
     dtau = np.diff(nodes) * dt
     U0 = np.array(U0, copy=True)
     F0 = f(U0, t0)
@@ -114,6 +134,7 @@ def sdc_run(f, U0, t0, dt, nodes, K, nsteps, perturb=None):
         times = tn + nodes * dt
         Uk = [U0] * (M + 1)
         Fk = [F0] * (M + 1)
+        rprev = None
         for k in range(K):
             Un = [U0]
             Fn = [F0]
@@ -124,6 +145,15 @@ def sdc_run(f, U0, t0, dt, nodes, K, nsteps, perturb=None):
                 Un.append(perturb(Un[m] + dtau[m] * (Fn[m] - Fk[m]) + dt * SF))
             Fn.append(f(Un[M], times[M]))
             Uk, Fk = Un, Fn
+            if residual_ratio > 0 and k < K - 1:
+                r = sdc_residual(U0, Fk, Uk[M], q, dt)
+                if history is not None:
+                    history.append((n, k, r))
+                if r == 0.0 or (rprev is not None and rprev < residual_ratio * r):
+                    break
+                rprev = r
+        if history is not None:
+            history.append(("sweeps", k + 1))
         U0, F0 = Uk[M], Fk[M]
     return U0
 

@@ -115,3 +115,42 @@ def test_mrsdc_fourth_order_with_three_coarse_nodes():
             errs.append(np.abs(u - exact).max())
         rate = math.log2(errs[1] / errs[2])
         assert rate == pytest.approx(4.0, abs=0.3), (n_fine, rep, errs)
+
+
+def test_residual_is_the_collocation_defect():
+    """sdc_residual against the same defect formed independently: the
+    polynomial through the node values of F integrated exactly over the step
+    (numpy's polynomial fit and integral), eq. (residual)."""
+    rng = np.random.default_rng(4)
+    nodes = sdc.gauss_lobatto(4)
+    q = sdc.s_matrix(nodes).sum(axis=0)
+    dt = 0.7
+    U0 = rng.standard_normal((3, 5)) + 2.0
+    F = [rng.standard_normal((3, 5)) for _ in nodes]
+    UM = rng.standard_normal((3, 5))
+    Fa = np.stack(F)                                     # [node][comp][cell]
+    coef = np.polynomial.polynomial.polyfit(nodes, Fa.reshape(len(nodes), -1), len(nodes) - 1)
+    integ = np.polynomial.polynomial.polyval(1.0, np.polynomial.polynomial.polyint(coef)) - \
+        np.polynomial.polynomial.polyval(0.0, np.polynomial.polynomial.polyint(coef))
+    R = U0 + dt * integ.reshape(3, 5) - UM
+    expect = max(np.abs(R[c]).max() / np.abs(U0[c]).max() for c in range(3))
+    assert abs(sdc.sdc_residual(U0, F, UM, q, dt) - expect) <= 1e-13 * expect
+
+
+def test_residual_exit_stops_at_the_collocation_solution():
+    """With the early exit the sweeps stop once the residual stagnates, and
+    the result is the collocation solution ((3,3) Pade value for GL4)."""
+    nodes = sdc.gauss_lobatto(4)
+    z = -0.5
+    f = lambda u, t: z * u
+    hist = []
+    u = sdc.sdc_run(f, np.array([1.0]), 0.0, 1.0, nodes, 40, 1, residual_ratio=1.5, history=hist)
+    pade = (1 + z / 2 + z * z / 10 + z ** 3 / 120) / (1 - z / 2 + z * z / 10 - z ** 3 / 120)
+    assert abs(u[0] - pade) < 1e-14
+    sweeps = [h[1] for h in hist if h[0] == "sweeps"][0]
+    assert 5 < sweeps < 40
+    rs = [h[2] for h in hist if h[0] != "sweeps"]
+    assert rs[-1] < 1e-15 and rs[0] > 1e-4
+    # residual_ratio = 0 keeps the fixed sweep count
+    u40 = sdc.sdc_run(f, np.array([1.0]), 0.0, 1.0, nodes, 40, 1)
+    np.testing.assert_array_equal(u40, sdc.sdc_run(f, np.array([1.0]), 0.0, 1.0, nodes, 40, 1, residual_ratio=0.0))
