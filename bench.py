@@ -94,7 +94,8 @@ def cpu_baseline(workload, mech, n_cells_full):
     t0 = time.perf_counter()
     if sch["kind"] == "sdc":
         f = lambda U, t: oracle.rhs(om, U, dx, nthreads=threads)
-        osdc.sdc_run(f, U0, 0.0, dt, osdc.gauss_lobatto(sch["n_coarse"]), sch["sweeps"], 1)
+        osdc.sdc_run(f, U0, 0.0, dt, osdc.gauss_lobatto(sch["n_coarse"]), sch["sweeps"], 1,
+                     residual_ratio=wl.get("residual_ratio", 0.0))
     else:
         f1 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.AD, nthreads=threads)
         f2 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.REACT, nthreads=threads)
@@ -375,6 +376,7 @@ def main():
     ctx = N.Context(0)
     ctx.set_mechanism(mech)
     ctx.set_reference_species(wl.get("ref_species", -1))
+    ctx.set_residual_exit(wl.get("residual_ratio", 0.0))
     prim = make_primitives(args.workload, mech)
     bx = N.box(nx, ny, nz, dx)
     U = torch.zeros(N.ghosted_shape(5 + ns, nz, ny, nx), dtype=torch.float64, device="cuda")
@@ -397,6 +399,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.check_status()
+    _, sweeps_done = ctx.residual_history()
     import ctypes
     tot = (ctypes.c_double * 32)()
     cnt = (ctypes.c_int * 32)()
@@ -409,8 +412,9 @@ def main():
     el = t1 - t0
     steps_per_s = args.steps / el
     M1 = sch_d["n_coarse"] - 1
-    n_ad = args.steps * sch_d["sweeps"] * M1
-    n_r = args.steps * sch_d["sweeps"] * M1 * r if r else n_ad
+    # with the residual early exit the sweeps taken replace K per step
+    n_ad = (sweeps_done if wl.get("residual_ratio") else args.steps * sch_d["sweeps"]) * M1
+    n_r = n_ad * r if r else n_ad
     model = work_model(ns, mech["nr"], sch_d["n_coarse"], r)
     dominant = max(kern, key=lambda k: kern[k][0])
     dur_ms = kern[dominant][0] / kern[dominant][1]
@@ -450,6 +454,7 @@ def main():
                    "scheme": sch_d, "dt": dt, "species_diffusion":
                    ("reference species %d" % wl["ref_species"]) if wl.get("ref_species", -1) >= 0
                    else "correction velocity"},
+        "sweeps_per_step": sweeps_done / args.steps,
         "mcell_ad_evals_per_s": ncell * n_ad / el / 1e6,
         "mcell_r_evals_per_s": ncell * n_r / el / 1e6,
         "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},

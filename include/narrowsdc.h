@@ -139,6 +139,26 @@ int sdc_step_batched(sdc_context *ctx, int nbox, const box_desc *boxes, double *
                      double dt, int nsteps, const sdc_scheme *scheme, void *workspace,
                      size_t ws_bytes, void *stream);
 
+/* SDC residual early exit (the residual of eq. residual, R^k = U_0 +
+ * dt q.F^k - U_M^k, q the last row of the integration matrix): ratio = 0
+ * (default) runs every step's K sweeps; ratio > 1 measures |R^k| after every
+ * sweep but a step's last and skips the step's remaining sweeps once
+ * |R^{k-1}| / |R^k| < ratio (the sweeps no longer approach the collocation
+ * solution).  |R| is the largest over state components of max|R_c| /
+ * max|U_0,c| over the interior.  Each measurement synchronises the stream
+ * (the decision is made on the host), so such steps are never captured in a
+ * graph.  Covers single-rate sdc_step on one box: sdc_step_batched and
+ * multirate schemes return SDC_EINVAL while it is on, and so do rhs_vjp and
+ * sdc_step_vjp.  Enabling it allocates a small device buffer (kept until the
+ * context is destroyed).  Errors: SDC_EINVAL for 0 < ratio <= 1 or ratio < 0. */
+int sdc_set_residual_exit(sdc_context *ctx, double ratio);
+
+/* The residuals |R^k| measured by the last sdc_step call, in order (the
+ * first max of them into norms, host memory), how many there were
+ * (count) and the sweeps the call performed over all its steps (sweeps);
+ * count and sweeps may be null. */
+int sdc_residual_history(const sdc_context *ctx, int max, double *norms, int *count, int *sweeps);
+
 /* Graph mode (enable != 0): sdc_step / sdc_step_batched on a non-null stream
  * capture all launches of a call into a HIP graph the first time and replay
  * it for calls with identical arguments (same boxes, state pointers, dt,

@@ -219,7 +219,7 @@ static const char *KERNEL_NAMES[K_NKERNELS] = {
     "prim_to_cons", "ghost",     "prims",     "vgrad",     "dir_x",     "dir_y",
     "dir_z",        "chem",      "sdc_node",  "mr_fine",   "mr_src",    "dir_adj_x",
     "dir_adj_y",    "dir_adj_z", "chem_adj",  "vgrad_adj", "prims_adj", "fold",
-    "adj_linalg"};
+    "adj_linalg",   "sdc_resid"};
 
 struct sdc_context {
   int device = 0;
@@ -249,6 +249,11 @@ struct sdc_context {
   int n_cu = 0;
   // captured step graphs
   bool use_graph = false;
+  // SDC residual early exit (single-rate sdc_step): ratio 0 = off
+  double resid_ratio = 0.0;
+  double *d_resid = nullptr;            // [NSDC_RESID_BLOCKS + 1][2 nU max] partial maxima, result
+  std::vector<double> resid_hist;       // residuals measured by the last sdc_step call
+  int last_sweeps = 0;                  // sweeps performed by the last sdc_step call
   std::map<std::string, hipGraphExec_t> graphs;
 };
 
@@ -536,11 +541,25 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
       FB[m] = W + L.F1 + fI * (M + m);
     }
     FRef Ub[2] = {FRef{W + L.Ub, nullptr}, FRef{W + L.Ub + fS, nullptr}};
+    // residual early exit (eq. residual): q = last row of the integration
+    // matrix, the sum of the node-to-node rows
+    const bool resid = c->resid_ratio > 0.0;
+    ResidArgs ra{};
+    if (resid) {
+      for (int j = 0; j <= M; ++j)
+        for (int m = 0; m < M; ++m) ra.q[j] += Sm[m][j];
+      ra.nnodes = M + 1;
+      ra.dt = dt;
+      ra.partial = c->d_resid;
+      ra.out = c->d_resid + (size_t)NSDC_RESID_BLOCKS * 2 * nU;
+    }
     eval_rhs_g(o, l, Uuser, P, G, FRef{F0, nullptr}, RHS_ALL);
     for (int step = 0; step < nsteps; ++step) {
       const double *Fold[8];
       for (int j = 0; j <= M; ++j) Fold[j] = F0;
       double *Fnew[8];
+      double rprev = -1.0;
+      int kdone = K;
       for (int k = 0; k < K; ++k) {
         Fnew[0] = F0;
         for (int m = 1; m <= M; ++m) Fnew[m] = (k % 2 == 0) ? FA[m] : FB[m];
@@ -564,7 +583,28 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
         const bool last = step == nsteps - 1 && k == K - 1;
         if (!last) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL, true);
         for (int j = 0; j <= M; ++j) Fold[j] = Fnew[j];
+        if (resid && k < K - 1) {
+          // |R^k| on the host (a synchronisation per sweep); stop the step's
+          // sweeps once it no longer shrinks by the ratio
+          for (int j = 0; j <= M; ++j) ra.F[j] = Fnew[j];
+          o->sdc_resid(l, Uuser, Ucur, ra);
+          double h[2 * NSDC_NSMAX + 10];
+          HIPCHECK(c, hipMemcpyAsync(h, ra.out, sizeof(double) * 2 * nU, hipMemcpyDeviceToHost, st));
+          HIPCHECK(c, hipStreamSynchronize(st));
+          double r = 0.0;
+          for (int q = 0; q < nU; ++q)
+            if (h[nU + q] > 0.0) r = std::max(r, h[q] / h[nU + q]);
+          c->resid_hist.push_back(r);
+          if (r == 0.0 || (rprev >= 0.0 && rprev < c->resid_ratio * r)) {
+            // the step ends with this sweep's end state (in a sweep buffer)
+            HIPCHECK(c, hipMemcpyAsync(Uuser.base, Ucur.base, sizeof(double) * fS, hipMemcpyDeviceToDevice, st));
+            kdone = k + 1;
+            break;
+          }
+          rprev = r;
+        }
       }
+      c->last_sweeps += kdone;
       if (step < nsteps - 1) {
         // recycle f(U_M) as the next step's f(U_0): exchange array roles
         double *fin = Fnew[M];
@@ -695,6 +735,7 @@ int sdc_context_destroy(sdc_context *c) {
   if (c->d_mech) (void)hipFree(c->d_mech);
   if (c->scratch) (void)hipFree(c->scratch);
   if (c->d_fine) (void)hipFree(c->d_fine);
+  if (c->d_resid) (void)hipFree(c->d_resid);
   delete c;
   return SDC_OK;
 }
@@ -867,6 +908,10 @@ namespace {
 int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U, double dt,
                int nsteps, const sdc_scheme *scheme, void *workspace, size_t ws_bytes,
                hipStream_t stream) {
+  c->resid_hist.clear();
+  c->last_sweeps = 0;
+  if (c->resid_ratio > 0.0 && (nbox > 1 || scheme->n_fine != 0))
+    return fail(c, SDC_EINVAL, "the residual early exit covers single-rate sdc_step only");
   Plan *pl;
   int rc = get_plan(c, nbox, boxes, nbox > 1 ? U : nullptr, &pl);
   if (rc) return rc;
@@ -875,7 +920,8 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
     rc = fine_tables(c, scheme);
     if (rc) return rc;
   }
-  if (!c->use_graph || !stream || c->prof) {
+  // (the residual early exit reads residuals on the host: no graph)
+  if (!c->use_graph || !stream || c->prof || c->resid_ratio > 0.0) {
     rc = run_sdc(c, pl, Uref, dt, nsteps, scheme, workspace, ws_bytes, stream);
     if (rc) return rc;
     HIPCHECK(c, hipGetLastError());
@@ -945,6 +991,26 @@ int sdc_step_batched(sdc_context *c, int nbox, const box_desc *boxes, double *co
   if (!(dt > 0) || nsteps < 1) return fail(c, SDC_EINVAL, "dt must be > 0 and nsteps >= 1");
   HIPCHECK(c, hipSetDevice(c->device));
   return step_entry(c, nbox, boxes, U, dt, nsteps, scheme, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int sdc_set_residual_exit(sdc_context *c, double ratio) {
+  if (!c) return SDC_EINVAL;
+  if (!(ratio == 0.0 || ratio > 1.0)) return fail(c, SDC_EINVAL, "residual ratio must be 0 (off) or > 1");
+  if (ratio > 0.0 && !c->d_resid) {
+    HIPCHECK(c, hipSetDevice(c->device));
+    HIPCHECK(c, hipMalloc(&c->d_resid, sizeof(double) * (NSDC_RESID_BLOCKS + 1) * 2 * (5 + NSDC_NSMAX)));
+  }
+  c->resid_ratio = ratio;
+  return SDC_OK;
+}
+
+int sdc_residual_history(const sdc_context *c, int max, double *norms, int *count, int *sweeps) {
+  if (!c || max < 0 || (max > 0 && !norms)) return SDC_EINVAL;
+  const int n = (int)c->resid_hist.size();
+  for (int i = 0; i < n && i < max; ++i) norms[i] = c->resid_hist[i];
+  if (count) *count = n;
+  if (sweeps) *sweeps = c->last_sweeps;
+  return SDC_OK;
 }
 
 int sdc_set_graph(sdc_context *c, int enable) {
@@ -1190,6 +1256,7 @@ int check_vjp_args(sdc_context *c, const box_desc *box) {
   if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
   if (c->h_mech.ref >= 0)
     return fail(c, SDC_EINVAL, "the adjoint covers the correction-velocity form of the species diffusion only");
+  if (c->resid_ratio > 0.0) return fail(c, SDC_EINVAL, "the adjoint covers fixed sweep counts only");
   int rc = check_box(c, box);
   if (rc) return rc;
   const TileShape t = c->forceI;

@@ -613,6 +613,73 @@ __global__ __launch_bounds__(256) void k_sdc_node(const BoxDev *__restrict__ box
   }
 }
 
+// Residual of eq. (residual) after a sweep: per component the largest |R|,
+// R = U_0 + dt sum_j q_j F_j - U_M, and the largest |U_0| over the interior
+// cells of the workgroup's items (a grid of at most NSDC_RESID_BLOCKS
+// workgroups), written to partial[block][2 NU]; maxima are independent of
+// the order, so the result is deterministic.
+template <int NS>
+__global__ __launch_bounds__(256) void k_sdc_resid(const BoxDev *__restrict__ boxes,
+                                                   const Item *__restrict__ items, int nitems,
+                                                   TileShape ts, FRef U0ref, FRef UMref, ResidArgs a) {
+  constexpr int NU = 5 + NS;
+  __shared__ double red[256];
+  double rmax[NU], umax[NU];
+#pragma unroll
+  for (int q = 0; q < NU; ++q) rmax[q] = umax[q] = 0.0;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+    const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+    const long long i = ((long long)z * b.ny + y) * b.nx + x;
+    const long long oI = b.offI * NU;
+    const double *U0 = U0ref.get(w.box, b.offS * NU);
+    const double *UM = UMref.get(w.box, b.offS * NU);
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+      const long long qi = oI + q * nI + i;
+      double sf = 0.0;
+      for (int j = 0; j < a.nnodes; ++j) sf += a.q[j] * a.F[j][qi];
+      const double u0 = U0[q * nS + s];
+      rmax[q] = fmax(rmax[q], fabs(u0 + a.dt * sf - UM[q * nS + s]));
+      umax[q] = fmax(umax[q], fabs(u0));
+    }
+  }
+  const int t = threadIdx.x, nt = blockDim.x;
+#pragma unroll
+  for (int v = 0; v < 2 * NU; ++v) {
+    red[t] = v < NU ? rmax[v] : umax[v - NU];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (t < h && t + h < nt) red[t] = fmax(red[t], red[t + h]);
+      __syncthreads();
+    }
+    if (t == 0) a.partial[blockIdx.x * 2 * NU + v] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[v] = max over the nblocks rows of partial[.][v]: workgroup v of ncol,
+// 256 threads striding over the rows, then a tree in LDS.
+__global__ __launch_bounds__(256) void k_rows_max(const double *__restrict__ partial, int nblocks, int ncol,
+                                                  double *__restrict__ out) {
+  __shared__ double red[256];
+  const int v = blockIdx.x, t = threadIdx.x;
+  double m = 0.0;
+  for (int b = t; b < nblocks; b += 256) m = fmax(m, partial[(long long)b * ncol + v]);
+  red[t] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] = fmax(red[t], red[t + h]);
+    __syncthreads();
+  }
+  if (t == 0) out[v] = red[0];
+}
+
 // One coarse interval of the multirate sweep, mode 1 (eq. mrupdate):
 //   U_{q+1} = U_q + dtau_q [f1(U^{k+1}_p) - f1(U^k_p)] + dtau_q [f2(U^{k+1}_q) - f2(U^k_q)]
 //             + dt S22_q . F2^k + dt S21_q . F1^k,
@@ -852,6 +919,14 @@ struct Launch {
                        c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Ucur, Unext, a);
     prof_end(c.prof, K_SDC_NODE, c.stream);
   }
+  static void sdc_resid(const LaunchCtx &c, FRef U0, FRef UM, const ResidArgs &a) {
+    const int nb = grid_for(c.nI, NSDC_RESID_BLOCKS);
+    prof_begin(c.prof, K_SDC_RESID, c.stream);
+    hipLaunchKernelGGL(k_sdc_resid<NS>, dim3(nb), dim3(c.tsI.tx * c.tsI.ty * c.tsI.tz), 0, c.stream, c.boxes,
+                       c.itemsI, c.nI, c.tsI, U0, UM, a);
+    hipLaunchKernelGGL(k_rows_max, dim3(2 * (5 + NS)), dim3(256), 0, c.stream, a.partial, nb, 2 * (5 + NS), a.out);
+    prof_end(c.prof, K_SDC_RESID, c.stream);
+  }
   static void mr_fine(const LaunchCtx &c, FRef Uin, FRef Uout, const FineCoef *fc,
                       const FinePtrs &fp, double *A, long long aslot) {
     const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
@@ -884,6 +959,7 @@ static const Ops make_ops() {
   o.dir = &Launch<NS>::dir;
   o.chem = &Launch<NS>::chem;
   o.sdc_node = &Launch<NS>::sdc_node;
+  o.sdc_resid = &Launch<NS>::sdc_resid;
   o.mr_fine = &Launch<NS>::mr_fine;
   return o;
 }

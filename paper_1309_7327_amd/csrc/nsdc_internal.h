@@ -75,6 +75,19 @@ struct NodeArgs {
   double dtau, dt;
 };
 
+// SDC residual R = U_0 + dt q.F - U_M (eq. residual) of one step after a
+// sweep: per component the largest |R| and the largest |U_0| over the
+// interior cells, reduced to 2 nU values.  partial: [NSDC_RESID_BLOCKS][2 nU]
+// per-workgroup maxima, out: [2 nU].
+#define NSDC_RESID_BLOCKS 1024
+struct ResidArgs {
+  const double *F[8];   // F at the nodes 0..M (interior arrays)
+  double q[8];          // last row of the integration matrix (normalised step)
+  int nnodes;
+  double dt;
+  double *partial, *out;
+};
+
 // Coefficients of one coarse interval of the multirate sweep, in units of
 // the step: rows of S_{2,1} and S_{2,2} restricted to the interval's fine
 // nodes, and the fine sub-step lengths (device memory, one per interval).

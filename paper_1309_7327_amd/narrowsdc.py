@@ -65,6 +65,8 @@ _SIGS = {
     "rhs_vjp": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, _vp, _vp, ctypes.c_uint, _vp],
     "set_log_prefactors": [_vp, _vp],
     "set_reference_species": [_vp, _ip],
+    "sdc_set_residual_exit": [_vp, ctypes.c_double],
+    "sdc_residual_history": [_vp, _ip, _vp, _vp, _vp],
     "sdc_vjp_workspace_size": [_vp, ctypes.POINTER(BoxDesc), ctypes.POINTER(Scheme), _ip,
                                ctypes.POINTER(ctypes.c_size_t)],
     "sdc_step_vjp": [_vp, ctypes.POINTER(BoxDesc), _vp, _d, _ip, ctypes.POINTER(Scheme), _vp, _vp, _vp,
@@ -204,6 +206,20 @@ class Context:
         """U_bar += (d rhs/dU)^T dUdt_bar; lnA_bar += (d rhs/d lnA)^T dUdt_bar."""
         self._check(_lib.rhs_vjp(self.h, ctypes.byref(bx), _ptr(U), _ptr(dUdt_bar), _ptr(U_bar),
                                  _ptr(lnA_bar), parts, _stream(stream)))
+
+    def set_residual_exit(self, ratio=0.0):
+        """0: K sweeps per step; ratio > 1: skip a step's remaining sweeps once
+        successive residuals of eq. (residual) shrink by less than ratio."""
+        self._check(_lib.sdc_set_residual_exit(self.h, float(ratio)))
+
+    def residual_history(self):
+        """(residuals measured by the last sdc_step call, sweeps it performed)."""
+        n, sw = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.sdc_residual_history(self.h, 0, None, ctypes.byref(n), ctypes.byref(sw)))
+        out = np.zeros(max(n.value, 1))
+        self._check(_lib.sdc_residual_history(self.h, n.value, ctypes.c_void_p(out.ctypes.data), ctypes.byref(n),
+                                              ctypes.byref(sw)))
+        return out[:n.value], sw.value
 
     def set_reference_species(self, k=-1):
         """-1: correction-velocity species diffusion (default); k >= 0:

@@ -13,6 +13,8 @@
   batch240_sdc    240 independent boxes with edges drawn from {16..48},
                   9/21, single-rate SDC as box16_sdc.
   box64_adjoint   64^3, 9/21, vector-Jacobian product of the right-hand side.
+  box64_sdc_resid 64^3, 9/21, single-rate SDC of up to 12 sweeps per step
+                  with the residual early exit (ratio 1.5), 5 steps.
 All with dx = 1e-4 m.  The time step of each workload is frozen in the
 manifest (tests/golden/manifest/dt.json).
 """
@@ -41,6 +43,9 @@ WORKLOADS = {
                          scheme=dict(kind="sdc", n_coarse=4, sweeps=6, n_fine=0), steps=1),
     "box64_adjoint": dict(shape=(64, 64, 64), dx=1e-4, mech="mech9", recipe="sines", seed=5,
                           scheme=dict(kind="sdc", n_coarse=4, sweeps=6, n_fine=0), steps=5),
+    "box64_sdc_resid": dict(shape=(64, 64, 64), dx=1e-4, mech="mech9", recipe="sines", seed=5,
+                            scheme=dict(kind="sdc", n_coarse=4, sweeps=12, n_fine=0), steps=5,
+                            residual_ratio=1.5),
 }
 
 

@@ -1,0 +1,105 @@
+"""SDC residual early exit (eq. residual): the HIP driver's residuals,
+sweep counts and end states against the oracle's, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sdc as osdc
+from synth import fields, mechanism
+from synth.workloads import time_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1309_7327_amd import narrowsdc as N  # noqa: E402
+import gpu_util as G  # noqa: E402
+
+
+def _ctx(kind):
+    m = mechanism.load(kind)
+    ctx = N.Context(0)
+    ctx.set_mechanism(m)
+    return m, oracle.Mechanism(m), ctx
+
+
+@pytest.mark.parametrize("kind,shape,K,ratio,nsteps", [
+    ("mech9", (8, 8, 8), 14, 1.5, 2),        # stops once the residual reaches rounding level
+    ("mech9le", (6, 5, 7), 10, 20.0, 1),     # stops after 3 sweeps, the residual still shrinking (ratios 122, 11)
+])
+def test_residual_exit_parity(kind, shape, K, ratio, nsteps):
+    m, om, ctx = _ctx(kind)
+    ctx.set_residual_exit(ratio)
+    prim = fields.sines(shape, 1e-4, m["ns"], 13)
+    bx, U = G.device_state(ctx, prim, 1e-4)
+    U0g = G.interior(G.host(U)).copy()
+    dt = time_step("box16_sdc")
+    s = N.scheme(4, K, 0, 1)
+    ws, nb = N.workspace(ctx, [bx], s)
+    ctx.sdc_step(bx, U, dt, nsteps, s, ws, nb)
+    ctx.check_status()
+    norms, sweeps = ctx.residual_history()
+    Ug = G.interior(G.host(U))
+    U0 = oracle.prim_to_cons(om, prim)
+    hist = []
+    f = lambda V, t: oracle.rhs(om, V, 1e-4)
+    ref = osdc.sdc_run(f, U0, 0.0, dt, osdc.gauss_lobatto(4), K, nsteps, residual_ratio=ratio, history=hist)
+    rs = np.array([h[2] for h in hist if h[0] != "sweeps"])
+    osw = [h[1] for h in hist if h[0] == "sweeps"]
+    print("sweeps", sweeps, osw, "residuals", norms, rs)
+    assert sweeps < nsteps * K
+    # the decisions agree where the residual is above rounding level; at
+    # rounding level a step may take one sweep more or less
+    assert abs(sweeps - sum(osw)) <= nsteps
+    # the residual is a difference of states of order one (relative to
+    # max|U_0|) formed in another rounding order: it agrees to rounding level
+    # in absolute terms, 1e-14 (about 50 ulp), and to 1e-6 where it is large
+    n = min(len(norms), len(rs))
+    np.testing.assert_allclose(norms[:n], rs[:n], rtol=1e-6, atol=1e-14)
+    _, floor, dfloor = G.ulp_floor_step(
+        lambda V, pt: osdc.sdc_run(f, V, 0.0, dt, osdc.gauss_lobatto(4), K, nsteps, pt, residual_ratio=ratio), U0)
+    ok, rep = G.compare(Ug, ref, floor)
+    okd, repd = G.compare(Ug - U0g, ref - U0, dfloor, state=ref)
+    print("U ", G.fmt(rep))
+    print("dU", G.fmt(repd))
+    assert ok and okd, G.fmt(repd)
+    ctx.close()
+
+
+def test_residual_exit_off_is_the_fixed_sweep_step_and_errors():
+    m, om, ctx = _ctx("mech9")
+    shape = (8, 9, 10)
+    prim = fields.sines(shape, 1e-4, m["ns"], 15)
+    dt = time_step("box16_sdc")
+    s = N.scheme(4, 6, 0, 1)
+    outs = []
+    for ratio in (1.5, 0.0):
+        ctx.set_residual_exit(ratio)
+        bx, U = G.device_state(ctx, prim, 1e-4)
+        ws, nb = N.workspace(ctx, [bx], s)
+        ctx.sdc_step(bx, U, dt, 1, s, ws, nb)
+        ctx.check_status()
+        outs.append((G.host(U), ctx.residual_history()))
+    assert outs[1][1][1] == 6 and len(outs[1][1][0]) == 0
+    # a fresh context (exit off by default) gives the same bits
+    m2, _, ctx2 = _ctx("mech9")
+    bx, U = G.device_state(ctx2, prim, 1e-4)
+    ws, nb = N.workspace(ctx2, [bx], s)
+    ctx2.sdc_step(bx, U, dt, 1, s, ws, nb)
+    np.testing.assert_array_equal(G.host(U), outs[1][0])
+    ctx2.close()
+    for bad in (0.5, 1.0, -2.0):
+        with pytest.raises(N.NarrowSDCError):
+            ctx.set_residual_exit(bad)
+    ctx.set_residual_exit(1.5)
+    bx, U = G.device_state(ctx, prim, 1e-4)
+    with pytest.raises(N.NarrowSDCError):          # multirate scheme
+        smr = N.scheme(4, 6, 5, 1)
+        ws, nb = N.workspace(ctx, [bx], smr)
+        ctx.sdc_step(bx, U, dt, 1, smr, ws, nb)
+    with pytest.raises(N.NarrowSDCError):          # the adjoint
+        v = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
+        ctx.rhs_vjp(bx, U, v, torch.zeros_like(v))
+    ctx.close()
