@@ -44,7 +44,7 @@ class _OMech(ctypes.Structure):
         ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("mu_exp", ctypes.c_double),
         ("Pr", ctypes.c_double), ("bulk_ratio", ctypes.c_double),
         ("m47", ctypes.c_double), ("m48", ctypes.c_double),
-        ("ref_species", ctypes.c_int),
+        ("ref_species", ctypes.c_int), ("wide_stencil", ctypes.c_int),
     ]
 
 
@@ -100,9 +100,11 @@ def _f64(a):
 class Mechanism:
     """Holds contiguous copies of a mechanism dict and its C descriptor.
     ref_species: -1 for the correction-velocity form of the species
-    diffusion, k >= 0 for reference species k (Section 2.1)."""
+    diffusion, k >= 0 for reference species k (Section 2.1).  wide: the
+    wide stencil D(a D u) instead of the narrow one for the second-derivative
+    terms (Section 2.2)."""
 
-    def __init__(self, mech, ref_species=-1):
+    def __init__(self, mech, ref_species=-1, wide=False):
         self.mech = mech
         self.ns = int(mech["ns"])
         self.nr = int(mech["nr"])
@@ -117,8 +119,9 @@ class Mechanism:
             _ptr(k["A"]).value, _ptr(k["b"]).value, _ptr(k["Ea"]).value,
             _ptr(k["nu_f"]).value, _ptr(k["nu_r"]).value, _ptr(k["Le"]).value,
             mech["mu_ref"], mech["T_ref"], mech["mu_exp"], mech["Pr"], mech["bulk_ratio"],
-            mech["m47"], mech["m48"], int(ref_species))
+            mech["m47"], mech["m48"], int(ref_species), int(bool(wide)))
         self.ref_species = int(ref_species)
+        self.wide = bool(wide)
 
     @property
     def ref(self):

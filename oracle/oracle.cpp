@@ -119,13 +119,15 @@ struct Mech {
   std::vector<int> nuf, nur;
   double Tlo, Thi, mu_ref, T_ref, mu_exp, Pr, bulk;
   int ref;   // -1 correction velocity, else the reference species
+  int wide;  // 1: wide stencil D(a D u) for the second-derivative pairs
   double M[8][8];
   explicit Mech(const omech *m)
       : ns(m->ns), nr(m->nr), W(m->W, m->W + m->ns), nasa(m->nasa, m->nasa + 7 * m->ns),
         A(m->A, m->A + m->nr), b(m->b, m->b + m->nr), Ea(m->Ea, m->Ea + m->nr),
         Le(m->Le, m->Le + m->ns), nuf(m->nu_f, m->nu_f + m->nr * m->ns),
         nur(m->nu_r, m->nu_r + m->nr * m->ns), Tlo(m->Tlo), Thi(m->Thi), mu_ref(m->mu_ref),
-        T_ref(m->T_ref), mu_exp(m->mu_exp), Pr(m->Pr), bulk(m->bulk_ratio), ref(m->ref_species) {
+        T_ref(m->T_ref), mu_exp(m->mu_exp), Pr(m->Pr), bulk(m->bulk_ratio), ref(m->ref_species),
+        wide(m->wide_stencil) {
     narrow8(m->m47, m->m48, M);
   }
 };
@@ -330,9 +332,11 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
   const long n = g.n();
   for (int q = 0; q < nU; ++q) out[q] = 0.0;
   const long c0 = g.at(i, j, k);
+  // stored index of the cell s steps along direction d (periodic images:
+  // the wide operator reaches 8 cells, past the 4 ghost layers)
   auto pt = [&](int d, int s) {
     int ii = i, jj = j, kk = k;
-    if (d == 0) ii += s; else if (d == 1) jj += s; else kk += s;
+    if (d == 0) ii = wrap(i + s, g.nx); else if (d == 1) jj = wrap(j + s, g.ny); else kk = wrap(k + s, g.nz);
     return g.at(ii, jj, kk);
   };
   // D_jdir u_comp at stored index c (c must have 4 neighbours along jdir)
@@ -342,7 +346,18 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
     for (int s = -4; s <= 4; ++s) f[s + 4] = g.u[comp][c + s * stride];
     return d1(f, g.dx[jdir]);
   };
-  S f[9], a[9], uu[9];
+  // second-derivative pairs L_d(a, u): a and u sampled at s = -R..R (index
+  // s + 8); narrow stencil (eq. H) from s = -4..4, or with the wide stencil
+  // D(a D u): the eighth-order first derivative of a times the first
+  // derivative of u, which reaches s = -8..8 (Section 2.2)
+  S f[9], a[17], uu[17];
+  const int R = m.wide ? 8 : 4;
+  auto pair = [&](const S *aa, const S *uv, double h) -> S {
+    if (!m.wide) return narrow(aa + 4, uv + 4, h, m.M);
+    S g9[9];
+    for (int o = -4; o <= 4; ++o) g9[o + 4] = aa[o + 8] * d1(uv + o + 4, h);
+    return d1(g9, h);
+  };
 
   if (parts & ORC_HYP) {
     for (int d = 0; d < 3; ++d) {
@@ -370,33 +385,33 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
       const double h = g.dx[d];
       // viscous momentum terms
       for (int ic = 0; ic < 3; ++ic) {
-        for (int s = -4; s <= 4; ++s) {
+        for (int s = -R; s <= R; ++s) {
           long c = pt(d, s);
-          a[s + 4] = ic == d ? 4.0 / 3.0 * g.mu[c] + g.xi[c] : g.mu[c];
-          uu[s + 4] = g.u[ic][c];
+          a[s + 8] = ic == d ? 4.0 / 3.0 * g.mu[c] + g.xi[c] : g.mu[c];
+          uu[s + 8] = g.u[ic][c];
         }
-        out[1 + ic] = out[1 + ic] + narrow(a, uu, h, m.M);
+        out[1 + ic] = out[1 + ic] + pair(a, uu, h);
       }
       // heat conduction
-      for (int s = -4; s <= 4; ++s) {
+      for (int s = -R; s <= R; ++s) {
         long c = pt(d, s);
-        a[s + 4] = g.lam[c];
-        uu[s + 4] = g.T[c];
+        a[s + 8] = g.lam[c];
+        uu[s + 8] = g.T[c];
       }
-      out[4] = out[4] + narrow(a, uu, h, m.M);
+      out[4] = out[4] + pair(a, uu, h);
       // viscous work, second-derivative parts
-      for (int s = -4; s <= 4; ++s) {
+      for (int s = -R; s <= R; ++s) {
         long c = pt(d, s);
-        a[s + 4] = g.mu[c];
-        uu[s + 4] = 0.5 * (g.u[0][c] * g.u[0][c] + g.u[1][c] * g.u[1][c] + g.u[2][c] * g.u[2][c]);
+        a[s + 8] = g.mu[c];
+        uu[s + 8] = 0.5 * (g.u[0][c] * g.u[0][c] + g.u[1][c] * g.u[1][c] + g.u[2][c] * g.u[2][c]);
       }
-      out[4] = out[4] + narrow(a, uu, h, m.M);
-      for (int s = -4; s <= 4; ++s) {
+      out[4] = out[4] + pair(a, uu, h);
+      for (int s = -R; s <= R; ++s) {
         long c = pt(d, s);
-        a[s + 4] = g.mu[c] / 3.0 + g.xi[c];
-        uu[s + 4] = 0.5 * g.u[d][c] * g.u[d][c];
+        a[s + 8] = g.mu[c] / 3.0 + g.xi[c];
+        uu[s + 8] = 0.5 * g.u[d][c] * g.u[d][c];
       }
-      out[4] = out[4] + narrow(a, uu, h, m.M);
+      out[4] = out[4] + pair(a, uu, h);
       // mixed first-derivative parts
       for (int ic = 0; ic < 3; ++ic) {
         if (ic == d) continue;
@@ -434,72 +449,72 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
         const int kr = m.ref;
         for (int ks = 0; ks < ns; ++ks) {
           if (ks == kr) continue;
-          for (int s = -4; s <= 4; ++s) {
+          for (int s = -R; s <= R; ++s) {
             long c = pt(d, s);
-            a[s + 4] = g.rhoD[ks * n + c];
-            uu[s + 4] = g.X[ks * n + c];
+            a[s + 8] = g.rhoD[ks * n + c];
+            uu[s + 8] = g.X[ks * n + c];
           }
-          S Lx = narrow(a, uu, h, m.M);
-          for (int s = -4; s <= 4; ++s) {
+          S Lx = pair(a, uu, h);
+          for (int s = -R; s <= R; ++s) {
             long c = pt(d, s);
-            a[s + 4] = g.rhoD[ks * n + c] * (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
-            uu[s + 4] = g.p[c];
+            a[s + 8] = g.rhoD[ks * n + c] * (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
+            uu[s + 8] = g.p[c];
           }
-          S Lp = narrow(a, uu, h, m.M);
+          S Lp = pair(a, uu, h);
           out[5 + ks] = out[5 + ks] + Lx + Lp;
           out[5 + kr] = out[5 + kr] - (Lx + Lp);
-          for (int s = -4; s <= 4; ++s) {
+          for (int s = -R; s <= R; ++s) {
             long c = pt(d, s);
-            a[s + 4] = g.rhoD[ks * n + c] * (g.h[ks * n + c] - g.h[kr * n + c]);
-            uu[s + 4] = g.X[ks * n + c];
+            a[s + 8] = g.rhoD[ks * n + c] * (g.h[ks * n + c] - g.h[kr * n + c]);
+            uu[s + 8] = g.X[ks * n + c];
           }
-          out[4] = out[4] + narrow(a, uu, h, m.M);
+          out[4] = out[4] + pair(a, uu, h);
         }
-        for (int s = -4; s <= 4; ++s) {
+        for (int s = -R; s <= R; ++s) {
           long c = pt(d, s);
           S sum = 0.0;
           for (int ks = 0; ks < ns; ++ks)
             if (ks != kr)
               sum = sum + g.rhoD[ks * n + c] * (g.h[ks * n + c] - g.h[kr * n + c]) *
                               (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
-          a[s + 4] = sum;
-          uu[s + 4] = g.p[c];
+          a[s + 8] = sum;
+          uu[s + 8] = g.p[c];
         }
-        out[4] = out[4] + narrow(a, uu, h, m.M);
+        out[4] = out[4] + pair(a, uu, h);
         continue;
       }
       // species diffusion
       for (int ks = 0; ks < ns; ++ks) {
-        for (int s = -4; s <= 4; ++s) {
+        for (int s = -R; s <= R; ++s) {
           long c = pt(d, s);
-          a[s + 4] = g.rhoD[ks * n + c];
-          uu[s + 4] = g.X[ks * n + c];
+          a[s + 8] = g.rhoD[ks * n + c];
+          uu[s + 8] = g.X[ks * n + c];
         }
-        S Lx = narrow(a, uu, h, m.M);
-        for (int s = -4; s <= 4; ++s) {
+        S Lx = pair(a, uu, h);
+        for (int s = -R; s <= R; ++s) {
           long c = pt(d, s);
-          a[s + 4] = g.rhoD[ks * n + c] * (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
-          uu[s + 4] = g.p[c];
+          a[s + 8] = g.rhoD[ks * n + c] * (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
+          uu[s + 8] = g.p[c];
         }
-        S Lp = narrow(a, uu, h, m.M);
+        S Lp = pair(a, uu, h);
         out[5 + ks] = out[5 + ks] + Lx + Lp;
         divVc = divVc - (Lx + Lp);
-        for (int s = -4; s <= 4; ++s) {
+        for (int s = -R; s <= R; ++s) {
           long c = pt(d, s);
-          a[s + 4] = g.rhoD[ks * n + c] * g.h[ks * n + c];
-          uu[s + 4] = g.X[ks * n + c];
+          a[s + 8] = g.rhoD[ks * n + c] * g.h[ks * n + c];
+          uu[s + 8] = g.X[ks * n + c];
         }
-        out[4] = out[4] + narrow(a, uu, h, m.M);
+        out[4] = out[4] + pair(a, uu, h);
       }
-      for (int s = -4; s <= 4; ++s) {
+      for (int s = -R; s <= R; ++s) {
         long c = pt(d, s);
         S sum = 0.0;
         for (int ks = 0; ks < ns; ++ks)
           sum = sum + g.rhoD[ks * n + c] * g.h[ks * n + c] * (g.X[ks * n + c] - g.Y[ks * n + c]) / g.p[c];
-        a[s + 4] = sum;
-        uu[s + 4] = g.p[c];
+        a[s + 8] = sum;
+        uu[s + 8] = g.p[c];
       }
-      out[4] = out[4] + narrow(a, uu, h, m.M);
+      out[4] = out[4] + pair(a, uu, h);
       // correction velocity component d, first derivatives of Y_k and h_k Y_k
       for (int s = -4; s <= 4; ++s) f[s + 4] = g.p[pt(d, s)];
       S Dp = d1(f, h);

@@ -32,6 +32,9 @@ typedef struct {
      correction velocity; k >= 0 reference species k, whose flux is minus the
      sum of the others' mixture-model fluxes */
   int ref_species;
+  /* second derivatives (a u_x)_x: 0 the narrow stencil (eq. H), 1 the wide
+     stencil D(a D u) of two eighth-order first derivatives (Section 2.2) */
+  int wide_stencil;
 } omech;
 
 enum { ORC_HYP = 1, ORC_DIFF = 2, ORC_REACT = 4 };
