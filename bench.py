@@ -83,7 +83,7 @@ def cpu_baseline(workload, mech, n_cells_full):
     from oracle import sdc as osdc
     from synth.workloads import WORKLOADS, make_primitives, time_step
     wl = WORKLOADS[workload]
-    om = oracle.Mechanism(mech, ref_species=wl.get("ref_species", -1))
+    om = oracle.Mechanism(mech, ref_species=wl.get("ref_species", -1), wide=wl.get("wide", False))
     edge = 64
     prim = make_primitives(workload, mech, shape_override=(edge,) * 3)
     U0 = oracle.prim_to_cons(om, prim)
@@ -377,6 +377,7 @@ def main():
     ctx.set_mechanism(mech)
     ctx.set_reference_species(wl.get("ref_species", -1))
     ctx.set_residual_exit(wl.get("residual_ratio", 0.0))
+    ctx.set_wide_stencil(wl.get("wide", False))
     prim = make_primitives(args.workload, mech)
     bx = N.box(nx, ny, nz, dx)
     U = torch.zeros(N.ghosted_shape(5 + ns, nz, ny, nx), dtype=torch.float64, device="cuda")
@@ -451,16 +452,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": ncell, "species": ns, "reactions": int(mech["nr"]),
-                   "scheme": sch_d, "dt": dt, "species_diffusion":
+                   "scheme": sch_d, "dt": dt,
+                   "second_derivatives": "wide stencil D(a D u)" if wl.get("wide") else "narrow stencil",
+                   "species_diffusion":
                    ("reference species %d" % wl["ref_species"]) if wl.get("ref_species", -1) >= 0
                    else "correction velocity"},
-        "sweeps_per_step": sweeps_done / args.steps,
         "mcell_ad_evals_per_s": ncell * n_ad / el / 1e6,
         "mcell_r_evals_per_s": ncell * n_r / el / 1e6,
         "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},
         "roofline": roof,
         "hbm_copy_gbs": args.copy_gbs,
     }
+    if wl.get("residual_ratio"):
+        out["sweeps_per_step"] = sweeps_done / args.steps
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, mech, ncell)
     print(json.dumps(out), flush=True)

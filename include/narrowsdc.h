@@ -139,6 +139,15 @@ int sdc_step_batched(sdc_context *ctx, int nbox, const box_desc *boxes, double *
                      double dt, int nsteps, const sdc_scheme *scheme, void *workspace,
                      size_t ws_bytes, void *stream);
 
+/* Second derivatives (a u_x)_x of the viscous, conduction and diffusion
+ * terms (Section 2.2): enable = 0 (default) the eighth-order narrow stencil
+ * of eq. (H); enable != 0 the wide stencil D(a D u), two applications of the
+ * eighth-order first derivative, whose samples reach 8 cells (taken from the
+ * periodic images).  The wide operator is blind to the grid's odd-even
+ * mode, the reason the paper prefers the narrow one.  rhs_vjp and
+ * sdc_step_vjp return SDC_EINVAL while it is on. */
+int set_wide_stencil(sdc_context *ctx, int enable);
+
 /* SDC residual early exit (the residual of eq. residual, R^k = U_0 +
  * dt q.F^k - U_M^k, q the last row of the integration matrix): ratio = 0
  * (default) runs every step's K sweeps; ratio > 1 measures |R^k| after every

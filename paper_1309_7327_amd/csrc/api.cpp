@@ -250,6 +250,7 @@ struct sdc_context {
   // captured step graphs
   bool use_graph = false;
   // SDC residual early exit (single-rate sdc_step): ratio 0 = off
+  bool wide = false;                    // wide-stencil second derivatives
   double resid_ratio = 0.0;
   double *d_resid = nullptr;            // [NSDC_RESID_BLOCKS + 1][2 nU max] partial maxima, result
   std::vector<double> resid_hist;       // residuals measured by the last sdc_step call
@@ -411,6 +412,7 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.cap = c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : 1 << 30);
   l.mech = c->d_mech;
   l.ref_species = c->h_mech.ref;
+  l.wide = c->wide;
   l.err = c->d_err;
   l.prof = c->prof.get();
   l.smc_stencil = c->smc_stencil;
@@ -993,6 +995,12 @@ int sdc_step_batched(sdc_context *c, int nbox, const box_desc *boxes, double *co
   return step_entry(c, nbox, boxes, U, dt, nsteps, scheme, workspace, ws_bytes, (hipStream_t)stream);
 }
 
+int set_wide_stencil(sdc_context *c, int enable) {
+  if (!c) return SDC_EINVAL;
+  c->wide = enable != 0;
+  return SDC_OK;
+}
+
 int sdc_set_residual_exit(sdc_context *c, double ratio) {
   if (!c) return SDC_EINVAL;
   if (!(ratio == 0.0 || ratio > 1.0)) return fail(c, SDC_EINVAL, "residual ratio must be 0 (off) or > 1");
@@ -1257,6 +1265,7 @@ int check_vjp_args(sdc_context *c, const box_desc *box) {
   if (c->h_mech.ref >= 0)
     return fail(c, SDC_EINVAL, "the adjoint covers the correction-velocity form of the species diffusion only");
   if (c->resid_ratio > 0.0) return fail(c, SDC_EINVAL, "the adjoint covers fixed sweep counts only");
+  if (c->wide) return fail(c, SDC_EINVAL, "the adjoint covers the narrow stencil only");
   int rc = check_box(c, box);
   if (rc) return rc;
   const TileShape t = c->forceI;

@@ -248,8 +248,11 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
 // spill), two otherwise (larger spills cost more than the extra waves gain).
 // REF: the reference-species form of the species diffusion (its own
 // instance: the branch would otherwise raise the register use of both).
-template <int NS, int D, bool FIXED, bool REF>
-__global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
+// WIDE: the second-derivative pairs with the wide stencil D(a D u) of two
+// eighth-order first derivatives (Section 2.2) instead of the narrow one;
+// its u samples reach 8 cells along D, taken from the periodic images.
+template <int NS, int D, bool FIXED, bool REF, bool WIDE>
+__global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
                                              TileShape ts, FRef Uref,
                                              const double *__restrict__ Pbase,
@@ -303,6 +306,27 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const Bo
 #pragma unroll
       for (int o = 0; o < 9; ++o) v[o] = (f + (o - 4) * st)[s];
     };
+    // wide stencil: 17 samples along D (periodic images past the ghost
+    // layers), and v_o = w_o (D u)_o / idx with w the first-derivative
+    // weights, so that the pair (a, u) is dot9(a, v) idx2 as for B u
+    auto line17 = [&](const double *f, double *w) {
+      const int cD = D == 0 ? x : (D == 1 ? y : z), nDim = D == 0 ? b.nx : (D == 1 ? b.ny : b.nz);
+#pragma unroll
+      for (int o = 0; o < 17; ++o) {
+        const int c = ((cD + o - 8) % nDim + nDim) % nDim;
+        w[o] = f[(long long)s + (long long)(c - cD) * st];
+      }
+    };
+    auto wvec = [&](const double *w, double *v) {
+      constexpr double W[9] = {-C4, -C3, -C2, -C1, 0.0, C1, C2, C3, C4};
+#pragma unroll
+      for (int o = 0; o < 9; ++o) {
+        double du = 0.0;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) du += W[c] * w[o + c];
+        v[o] = W[o] * du;
+      }
+    };
     double ud[9], pp[9];
     line(P + (L::PU + D) * nS, ud);
     line(P + L::PP * nS, pp);
@@ -338,7 +362,53 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const Bo
     if (parts & 2) {  // diffusive terms
       const double bulk = m->bulk;
       const double lam2 = bulk - 2.0 / 3.0;
-      {
+      if constexpr (WIDE) {
+        // the same terms with the wide pairs
+        double mu[9], ke[17], fe[9], w[17], v[9], g[9];
+        line(P + L::PMU * nS, mu);
+#pragma unroll
+        for (int o = 0; o < 17; ++o) ke[o] = 0.0;
+#pragma unroll
+        for (int o = 0; o < 9; ++o) fe[o] = 0.0;
+#pragma unroll
+        for (int ic = 0; ic < 3; ++ic) {
+          line17(P + (L::PU + ic) * nS, w);
+          const double *u9 = w + 4;
+          wvec(w, v);
+          acc[1 + ic] += (ic == D ? 4.0 / 3.0 + bulk : 1.0) * dot9(mu, v) * idx2;
+#pragma unroll
+          for (int o = 0; o < 17; ++o) ke[o] += 0.5 * w[o] * w[o];
+          if (ic == D) {
+            line(G + (3 * J1 + J1) * nS, g);
+            line(G + (3 * J2 + J2) * nS, v);
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+              g[o] = lam2 * mu[o] * (g[o] + v[o]);
+              fe[o] += u9[o] * g[o];
+            }
+            acc[1 + D] += d1(g, idx);
+            double w2[17];
+#pragma unroll
+            for (int o = 0; o < 17; ++o) w2[o] = 0.5 * w[o] * w[o];
+            wvec(w2, v);
+            acc[4] += (1.0 / 3.0 + bulk) * dot9(mu, v) * idx2;
+          } else {
+            line(G + (3 * ic + D) * nS, g);
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+              g[o] *= mu[o];
+              fe[o] += u9[o] * g[o];
+            }
+            acc[1 + ic] += d1(g, idx);
+          }
+        }
+        wvec(ke, v);
+        acc[4] += dot9(mu, v) * idx2 + d1(fe, idx);
+        line17(P + L::PT * nS, w);
+        wvec(w, v);
+        line(P + L::PLAM * nS, g);
+        acc[4] += dot9(g, v) * idx2;
+      } else {
         double mu[9], ke[9], fe[9], u9[9], v[9], g[9];
         line(P + L::PMU * nS, mu);
 #pragma unroll
@@ -397,7 +467,26 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const Bo
       {
         double rd[9], wp[9], u9[9], v[9], g[9];
         line(P + L::PRD * nS, rd);
-        bvec<FIXED>(m, pp, v);
+        if constexpr (WIDE) {
+          double w[17];
+          line17(P + L::PP * nS, w);
+          wvec(w, v);
+        } else {
+          bvec<FIXED>(m, pp, v);
+        }
+        // X_k's centre samples into u9 and its pair vector into v
+        auto xpair = [&](const double *f, double *u9o, double *vo) {
+          if constexpr (WIDE) {
+            double w[17];
+            line17(f, w);
+#pragma unroll
+            for (int o = 0; o < 9; ++o) u9o[o] = w[o + 4];
+            wvec(w, vo);
+          } else {
+            line(f, u9o);
+            bvec<FIXED>(m, u9o, vo);
+          }
+        };
 #pragma unroll
         for (int o = 0; o < 9; ++o) wp[o] = rd[o] * v[o] / pp[o];
         const double Dpp = d1(pp, idx) / pp[4];
@@ -417,8 +506,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const Bo
             }
             if (k == ref) continue;
             const double iLe = m->invLe[k];
-            line(P + (L::PX + k) * nS, u9);
-            bvec<FIXED>(m, u9, v);
+            xpair(P + (L::PX + k) * nS, u9, v);
             line(P + (L::PY + k) * nS, g);
 #pragma unroll
             for (int o = 0; o < 9; ++o) u9[o] -= g[o];
@@ -464,10 +552,17 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const Bo
               line(U + (5 + k) * nS, y9);
               spc(k) -= d1p(y9, ud, idx);
             }
-            line(P + (L::PX + k) * nS, u9);
-            line(P + (L::PY + k) * nS, y9);
-            line(P + (L::PH + k) * nS, g);
-            bvec<FIXED>(m, u9, v);
+            if constexpr (WIDE) {
+              xpair(P + (L::PX + k) * nS, u9, v);
+              line(P + (L::PY + k) * nS, y9);
+              line(P + (L::PH + k) * nS, g);
+            } else {
+              // all three lines in flight before B X_k is formed
+              line(P + (L::PX + k) * nS, u9);
+              line(P + (L::PY + k) * nS, y9);
+              line(P + (L::PH + k) * nS, g);
+              bvec<FIXED>(m, u9, v);
+            }
             const double DX = d1(u9, idx);
             const double dXY4 = u9[4] - y9[4];
 #pragma unroll
@@ -502,8 +597,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 ? 3 : 2) void k_dir(const Bo
               line(U + (5 + k) * nS, u9);
               spc(k) -= d1p(u9, ud, idx);
             }
-            line(P + (L::PX + k) * nS, u9);
-            bvec<FIXED>(m, u9, v);
+            xpair(P + (L::PX + k) * nS, u9, v);
             const double DX = d1(u9, idx);
             line(P + (L::PY + k) * nS, g);
             const double dXY4 = u9[4] - g[4];
@@ -871,41 +965,43 @@ struct Launch {
                        c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, G);
     prof_end(c.prof, K_VGRAD, c.stream);
   }
-  template <bool FIXED>
-  static void dir_t(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F,
-                    unsigned parts) {
-    const TileShape ts = c.tsD[d];
-    const dim3 grid(grid_for(c.nD[d], c.cap)), block(ts.tx * ts.ty * ts.tz);
-    prof_begin(c.prof, K_DIR_X + d, c.stream);
-    if (c.ref_species >= 0) {
-      if (d == 0)
-        hipLaunchKernelGGL((k_dir<NS, 0, FIXED, true>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nD[0], ts,
-                           U, P, G, F, parts, c.mech);
-      else if (d == 1)
-        hipLaunchKernelGGL((k_dir<NS, 1, FIXED, true>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nD[1], ts,
-                           U, P, G, F, parts, c.mech);
-      else
-        hipLaunchKernelGGL((k_dir<NS, 2, FIXED, true>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nD[2], ts,
-                           U, P, G, F, parts, c.mech);
-    } else {
-      if (d == 0)
-        hipLaunchKernelGGL((k_dir<NS, 0, FIXED, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[0], c.nD[0], ts,
-                           U, P, G, F, parts, c.mech);
-      else if (d == 1)
-        hipLaunchKernelGGL((k_dir<NS, 1, FIXED, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[1], c.nD[1], ts,
-                           U, P, G, F, parts, c.mech);
-      else
-        hipLaunchKernelGGL((k_dir<NS, 2, FIXED, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[2], c.nD[2], ts,
-                           U, P, G, F, parts, c.mech);
-    }
-    prof_end(c.prof, K_DIR_X + d, c.stream);
+  template <int D, bool FIXED, bool REF, bool WIDE>
+  static void dir_k(const LaunchCtx &c, FRef U, const double *P, const double *G, FRef F, unsigned parts) {
+    const TileShape ts = c.tsD[D];
+    const dim3 grid(grid_for(c.nD[D], c.cap)), block(ts.tx * ts.ty * ts.tz);
+    hipLaunchKernelGGL((k_dir<NS, D, FIXED, REF, WIDE>), grid, block, 0, c.stream, c.boxes, c.itemsD[D], c.nD[D], ts,
+                       U, P, G, F, parts, c.mech);
+  }
+  template <bool FIXED, bool REF, bool WIDE>
+  static void dir_d(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F, unsigned parts) {
+    if (d == 0)
+      dir_k<0, FIXED, REF, WIDE>(c, U, P, G, F, parts);
+    else if (d == 1)
+      dir_k<1, FIXED, REF, WIDE>(c, U, P, G, F, parts);
+    else
+      dir_k<2, FIXED, REF, WIDE>(c, U, P, G, F, parts);
   }
   static void dir(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F,
                   unsigned parts) {
-    if (c.smc_stencil)
-      dir_t<true>(c, d, U, P, G, F, parts);
-    else
-      dir_t<false>(c, d, U, P, G, F, parts);
+    const bool ref = c.ref_species >= 0;
+    prof_begin(c.prof, K_DIR_X + d, c.stream);
+    if (c.wide) {   // (the wide pairs do not use the narrow matrix)
+      if (ref)
+        dir_d<true, true, true>(c, d, U, P, G, F, parts);
+      else
+        dir_d<true, false, true>(c, d, U, P, G, F, parts);
+    } else if (c.smc_stencil) {
+      if (ref)
+        dir_d<true, true, false>(c, d, U, P, G, F, parts);
+      else
+        dir_d<true, false, false>(c, d, U, P, G, F, parts);
+    } else {
+      if (ref)
+        dir_d<false, true, false>(c, d, U, P, G, F, parts);
+      else
+        dir_d<false, false, false>(c, d, U, P, G, F, parts);
+    }
+    prof_end(c.prof, K_DIR_X + d, c.stream);
   }
   static void chem(const LaunchCtx &c, FRef U, double *F2) {
     prof_begin(c.prof, K_CHEM, c.stream);

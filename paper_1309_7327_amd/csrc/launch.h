@@ -39,6 +39,7 @@ struct LaunchCtx {
   Profiler *prof;
   bool smc_stencil;   // the default narrow-stencil parameters: compile-time B
   int ref_species;    // species diffusion: -1 correction velocity, else the reference species
+  bool wide;          // second-derivative pairs with the wide stencil D(a D u)
 };
 
 struct Ops {

@@ -66,6 +66,7 @@ _SIGS = {
     "set_log_prefactors": [_vp, _vp],
     "set_reference_species": [_vp, _ip],
     "sdc_set_residual_exit": [_vp, ctypes.c_double],
+    "set_wide_stencil": [_vp, _ip],
     "sdc_residual_history": [_vp, _ip, _vp, _vp, _vp],
     "sdc_vjp_workspace_size": [_vp, ctypes.POINTER(BoxDesc), ctypes.POINTER(Scheme), _ip,
                                ctypes.POINTER(ctypes.c_size_t)],
@@ -206,6 +207,11 @@ class Context:
         """U_bar += (d rhs/dU)^T dUdt_bar; lnA_bar += (d rhs/d lnA)^T dUdt_bar."""
         self._check(_lib.rhs_vjp(self.h, ctypes.byref(bx), _ptr(U), _ptr(dUdt_bar), _ptr(U_bar),
                                  _ptr(lnA_bar), parts, _stream(stream)))
+
+    def set_wide_stencil(self, enable=True):
+        """Second derivatives with the wide stencil D(a D u) (Section 2.2)
+        instead of the narrow one."""
+        self._check(_lib.set_wide_stencil(self.h, 1 if enable else 0))
 
     def set_residual_exit(self, ratio=0.0):
         """0: K sweeps per step; ratio > 1: skip a step's remaining sweeps once

@@ -7,6 +7,8 @@
                   4 Gauss-Lobatto nodes, chemistry on 5 Gauss-Lobatto nodes in
                   each coarse interval (4 sub-steps per fluid node), 6 sweeps.
   box256_mrsdc    256^3, 21 species / 84 reactions, 5 multirate steps.
+  box128_mrsdc_wide   box128_mrsdc with the wide stencil D(a D u) for the
+                  second-derivative terms.
   box128_mrsdc_n2ref  box128_mrsdc's flame and scheme with the non-unity
                   Lewis number variant of the 9-species mechanism and N2 as
                   the reference species of the species diffusion.
@@ -34,6 +36,9 @@ WORKLOADS = {
                       scheme=dict(kind="sdc", n_coarse=4, sweeps=6, n_fine=0), steps=1),
     "box128_mrsdc": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9", recipe="turb", seed=2, kmax=16,
                          scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=10),
+    "box128_mrsdc_wide": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9", recipe="turb", seed=2, kmax=16,
+                              scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=10,
+                              wide=True),
     "box128_mrsdc_n2ref": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9le", recipe="turb", seed=2, kmax=16,
                                scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=10,
                                ref_species=8),
