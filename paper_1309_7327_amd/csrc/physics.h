@@ -23,7 +23,7 @@ constexpr double LN_RU_PREF = -9.408091968943316;  // ln(RU / PREF)
 constexpr double EXP_INV_LN2_64 = 92.33248261689366;        // 64 / ln 2
 constexpr double EXP_LN2_64_HI = 0.010830424696223417;      // 0x3f862e42fefa0000
 constexpr double EXP_LN2_64_LO = 2.572804622327669e-14;     // ln2/64 - HI
-__device__ __forceinline__ double exp_tab(double x, const double *tab) {
+__host__ __device__ __forceinline__ double exp_tab(double x, const double *tab) {
   const double kd = rint(x * EXP_INV_LN2_64);
   const int k = (int)kd;
   double r = fma(-kd, EXP_LN2_64_HI, x);
