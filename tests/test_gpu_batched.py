@@ -148,3 +148,26 @@ def test_autotuned_shapes_give_identical_results(setup):
     _run_batched(ctx, boxes, Ub, sch, 1, dt)
     for a, b in zip(Ua, Ub):
         assert torch.equal(G.interior(a), G.interior(b))
+
+
+@pytest.mark.parametrize("variant", ["reference_species", "wide_stencil"])
+def test_batched_variants_equal_per_box_loop(variant):
+    """The reference-species and wide-stencil instances of the stencil
+    passes walk the same (box, tile) work lists: batched = per-box loop."""
+    m = mechanism.load("mech9le")
+    ctx = N.Context(0)
+    ctx.set_mechanism(m)
+    if variant == "reference_species":
+        ctx.set_reference_species(8)
+    else:
+        ctx.set_wide_stencil(True)
+    idx = [0, 3, 8, 21]
+    dt = time_step("batch240_sdc")
+    sch = N.scheme(4, 4, 0, 1)
+    boxes, Ub = _states(ctx, m, idx)
+    _, Ul = _states(ctx, m, idx)
+    _run_batched(ctx, boxes, Ub, sch, 1, dt)
+    _run_loop(ctx, boxes, Ul, sch, 1, dt)
+    for a, b in zip(Ub, Ul):
+        assert torch.equal(G.interior(a), G.interior(b))
+    ctx.close()
