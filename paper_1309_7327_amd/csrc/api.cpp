@@ -775,6 +775,11 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
     d.h6[k] = a[5];
     for (int i = 0; i < 4; ++i) d.sc[k][i] = a[i + 1] / (i + 1);
     d.s7[k] = a[6];
+    d.gc[k][0] = a[0] - a[6];
+    d.gc[k][1] = -a[1] / 2.0;
+    d.gc[k][2] = -a[2] / 6.0;
+    d.gc[k][3] = -a[3] / 12.0;
+    d.gc[k][4] = -a[4] / 20.0;
   }
   for (int j = 0; j < 64; ++j) d.e2tab[j] = (double)exp2l((long double)j / 64.0L);
   for (int j = 0; j < m->nr; ++j) {

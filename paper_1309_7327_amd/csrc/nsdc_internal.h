@@ -28,6 +28,8 @@ struct DevMech {
   double h6[NSDC_NSMAX];      // a6
   double sc[NSDC_NSMAX][4];   // a2, a3/2, a4/3, a5/4
   double s7[NSDC_NSMAX];      // a7
+  // g/(RT) = h/(RT) - s/R = gc0 - a1 ln T + T (gc1 + T (gc2 + T (gc3 + T gc4))) + a6 / T
+  double gc[NSDC_NSMAX][5];   // a1 - a7, -a2/2, -a3/6, -a4/12, -a5/20
   double lnA[NSDC_NRMAX], beta[NSDC_NRMAX], EaR[NSDC_NRMAX];
   int rs[NSDC_NRMAX][2], ps[NSDC_NRMAX][2];
   int dnu[NSDC_NRMAX];

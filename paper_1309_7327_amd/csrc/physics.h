@@ -62,6 +62,12 @@ __device__ __forceinline__ double h_RT(const DevMech *__restrict__ m, int k, dou
   const double *a = m->hc[k];
   return a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4]))) + m->h6[k] * invT;
 }
+// g/(RT) of the reaction-rate equilibrium constants from the combined
+// coefficients (the h/(RT) and s/R polynomials folded into one)
+__device__ __forceinline__ double g_RT(const DevMech *__restrict__ m, int k, double T, double invT, double lnT) {
+  const double *c = m->gc[k];
+  return fma(m->h6[k], invT, fma(-m->cp[k][0], lnT, fma(T, c[1] + T * (c[2] + T * (c[3] + T * c[4])), c[0])));
+}
 __device__ __forceinline__ double s_R(const DevMech *__restrict__ m, int k, double T, double lnT) {
   const double *a = m->sc[k];
   return m->cp[k][0] * lnT + T * (a[0] + T * (a[1] + T * (a[2] + T * a[3]))) + m->s7[k];
@@ -120,7 +126,7 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     c[k] = rho * Y[k] * m->invW[k];
-    g[k] = h_RT(m, k, T, invT) - s_R(m, k, T, lnT);
+    g[k] = g_RT(m, k, T, invT, lnT);
     w[k] = 0.0;
   }
   c[NS] = 1.0;
@@ -165,7 +171,7 @@ __device__ void production_sh(const DevMech *__restrict__ m, double rho, double 
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     sh[k * S] = rho * Y[k] * m->invW[k];
-    sh[A + k * S] = h_RT(m, k, T, invT) - s_R(m, k, T, lnT);
+    sh[A + k * S] = g_RT(m, k, T, invT, lnT);
     sh[2 * A + k * S] = 0.0;
   }
   sh[NS * S] = 1.0;
