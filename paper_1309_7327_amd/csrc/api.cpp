@@ -251,6 +251,7 @@ struct sdc_context {
   bool use_graph = false;
   // SDC residual early exit (single-rate sdc_step): ratio 0 = off
   bool wide = false;                    // wide-stencil second derivatives
+  bool fused_fine = true;               // one-kernel multirate fine sub-steps (4 sub-steps, <= 9 species)
   double resid_ratio = 0.0;
   double *d_resid = nullptr;            // [NSDC_RESID_BLOCKS + 1][2 nU max] partial maxima, result
   std::vector<double> resid_hist;       // residuals measured by the last sdc_step call
@@ -413,6 +414,7 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.mech = c->d_mech;
   l.ref_species = c->h_mech.ref;
   l.wide = c->wide;
+  l.fused_fine = c->fused_fine;
   l.err = c->d_err;
   l.prof = c->prof.get();
   l.smc_stencil = c->smc_stencil;
@@ -506,6 +508,8 @@ int fine_tables(sdc_context *c, const sdc_scheme *s) {
                                    tf.begin() + piece * (s->n_fine - 1) + s->n_fine);
       f.jlo[q] = piece * (s->n_fine - 1);
       for (int j = 0; j < s->n_fine; ++j) f.S22[q][j] = (double)lagrange_integral(loc, j, tf[q], tf[q + 1]);
+      if (r == 4)
+        for (int j = 0; j < s->n_fine; ++j) f.S22n[q][f.jlo[q] + j] = f.S22[q][j];
     }
   }
   if (c->d_fine) (void)hipFree(c->d_fine);
@@ -676,6 +680,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
         fp.q0_known = pi == 0;
         fp.eval_last = (pi == M - 1) && !last;
         fp.nq = r;
+        fp.n1 = M + 1;
         fp.dt = dt;
         o->mr_fine(l, Uin, Uout, c->d_fine + pi, fp, W + L.A, fI);
       }
@@ -1003,6 +1008,12 @@ int sdc_step_batched(sdc_context *c, int nbox, const box_desc *boxes, double *co
 int set_wide_stencil(sdc_context *c, int enable) {
   if (!c) return SDC_EINVAL;
   c->wide = enable != 0;
+  return SDC_OK;
+}
+
+int sdc_set_fused_fine(sdc_context *c, int enable) {
+  if (!c) return SDC_EINVAL;
+  c->fused_fine = enable != 0;
   return SDC_OK;
 }
 

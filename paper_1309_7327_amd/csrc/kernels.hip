@@ -924,6 +924,152 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
   }
 }
 
+// The two kernels above fused for four coarse nodes, four fine sub-steps
+// and at most nine species: the interval's increments are formed in registers with k_mr_src's
+// arithmetic and consumed by k_mr_step's sub-steps without the round trip
+// through HBM (4 nU stores and loads per cell).  The chemistry changes only
+// the species components, so the other five follow from their increments
+// alone: the prologue runs them through all sub-steps and keeps just the
+// density and internal energy each temperature solve needs.  What stays live
+// over the sub-steps (4 Ns species increments, Ns partial densities, 2 x 5
+// scalars) fits the registers of the two waves per SIMD that the LDS column
+// allows.  Sub-step r reads row 0 of each array, which then shifts up by one,
+// so every register index is known at compile time.
+template <int NS>
+__global__ __launch_bounds__(256, 2) void k_mr_fused(const BoxDev *__restrict__ boxes,
+                                                     const Item *__restrict__ items, int nitems,
+                                                     TileShape ts, FRef Uin, FRef Uout,
+                                                     const FineCoef *__restrict__ fc, FinePtrs fp,
+                                                     const DevMech *__restrict__ m, int *err) {
+  constexpr int NU = 5 + NS, NQ = 4, N1 = 4;
+  NSDC_CHEM_LDS(NS, NSDC_CHEM_LDS_LIMIT, chem_sh);
+  double *sh = chem_lds_setup<NS, NSDC_CHEM_LDS_LIMIT>(chem_sh, m);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+    const unsigned s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+    const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
+    const long long o1 = b.offI * NU, o2 = b.offI * NS;
+    auto F1 = [&](int slot, int q) { return fp.F1base + (slot * fp.f1slot + o1 + q * nI); };
+    auto F2 = [&](int slot, int k) { return fp.F2base + (slot * fp.f2slot + o2 + k * nI); };
+    const double dt = fp.dt;
+    // the coefficients are read once per work item (hoisted out of the item
+    // loop they would stay live, in more scalar registers than there are,
+    // through the chemistry)
+    asm volatile("" ::: "memory");
+    double A[NQ][NU];
+    // A[r][q], sub-step r, component q (k_mr_src's arithmetic; the S22 rows
+    // padded with zeros to the interval's five fine nodes add exact zeros)
+    auto increments = [&](int q) __attribute__((always_inline)) {
+      double f1[N1];
+#pragma unroll
+      for (int j = 0; j < N1; ++j) f1[j] = F1(fp.F1old[j], q)[i];
+      const double dF1 = F1(fp.F1new_p, q)[i] - F1(fp.F1old_p, q)[i];
+      double g[NQ + 1];
+      if (q >= 5) {
+#pragma unroll
+        for (int j = 0; j <= NQ; ++j) g[j] = F2(fp.F2old[j], q - 5)[i];
+      }
+#pragma unroll
+      for (int r = 0; r < NQ; ++r) {
+        const double dtq = fc->dtq[r] * dt;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) acc += fc->S21[r][j] * f1[j];
+        double v = dtq * dF1 + dt * acc;
+        if (q >= 5) {
+          double s22 = 0.0;
+#pragma unroll
+          for (int j = 0; j <= NQ; ++j) s22 += fc->S22n[r][j] * g[j];
+          v += dt * s22 - dtq * g[r];
+        }
+        A[r][q] = v;
+      }
+    };
+    // the five non-species components first: their sub-step values are
+    // formed before the species' increments take registers
+#pragma unroll
+    for (int q = 0; q < 5; ++q) increments(q);
+    const double *Ui = Uin.get(w.box, b.offS * NU);
+    double *Uo = Uout.get(w.box, b.offS * NU);
+    // density and internal energy at sub-steps 0..NQ (as cell_state forms them)
+    double Un[5], rq[NQ + 1], eq[NQ + 1];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Un[c] = (Ui + c * nS)[s];
+#pragma unroll
+    for (int r = 0; r <= NQ; ++r) {
+      rq[r] = Un[0];
+      const double ir = 1.0 / Un[0];
+      const double ux = Un[1] * ir, uy = Un[2] * ir, uz = Un[3] * ir;
+      eq[r] = Un[4] * ir - 0.5 * (ux * ux + uy * uy + uz * uz);
+      if (r < NQ) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Un[c] += A[r][c];
+      }
+    }
+    // final values of the non-species components (each thread reads and
+    // writes only its own cell, so the in-place case is safe)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) (Uo + c * nS)[s] = Un[c];
+#pragma unroll
+    for (int q = 5; q < NU; ++q) increments(q);
+    double Ys[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Ys[k] = (Ui + (5 + k) * nS)[s];
+    int errs = 0;
+    double Tprev = 1000.0;
+#pragma unroll 1
+    for (int qq = 0; qq < NQ; ++qq) {
+      double f2[NS];
+      if (qq == 0 && fp.q0_known) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) f2[k] = F2(fp.F2old[0], k)[i];
+      } else {
+        double Y[NS], T;
+        const double ir = 1.0 / rq[0];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Y[k] = Ys[k] * ir;
+        errs |= rq[0] > 0.0 ? 0 : NSDC_ERR_RHO;
+        errs |= temperature<NS>(m, Y, eq[0], T, Tprev);
+        Tprev = T;
+        production_any<NS, NSDC_CHEM_LDS_LIMIT>(m, rq[0], T, Y, f2, sh);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) F2(fp.F2new[qq], k)[i] = f2[k];
+      }
+      const double dtq = fc->dtq[qq] * dt;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) Ys[k] += A[0][5 + k] + dtq * f2[k];
+#pragma unroll
+      for (int r = 0; r + 1 < NQ; ++r)
+#pragma unroll
+        for (int k = 0; k < NS; ++k) A[r][5 + k] = A[r + 1][5 + k];
+#pragma unroll
+      for (int r = 0; r < NQ; ++r) {
+        rq[r] = rq[r + 1];
+        eq[r] = eq[r + 1];
+      }
+    }
+    if (fp.eval_last) {
+      double Y[NS], T, f2[NS];
+      const double ir = 1.0 / rq[0];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) Y[k] = Ys[k] * ir;
+      errs |= rq[0] > 0.0 ? 0 : NSDC_ERR_RHO;
+      errs |= temperature<NS>(m, Y, eq[0], T, Tprev);
+      production_any<NS, NSDC_CHEM_LDS_LIMIT>(m, rq[0], T, Y, f2, sh);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) F2(fp.F2new[NQ], k)[i] = f2[k];
+    }
+    if (errs) atomicOr(err, errs);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) (Uo + (5 + k) * nS)[s] = Ys[k];
+  }
+}
+
 }  // namespace nsdc
 
 // ------------------------------------------------------------ launchers
@@ -1026,6 +1172,15 @@ struct Launch {
   static void mr_fine(const LaunchCtx &c, FRef Uin, FRef Uout, const FineCoef *fc,
                       const FinePtrs &fp, double *A, long long aslot) {
     const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
+    if constexpr (NS <= 9) {
+      if (fp.nq == 4 && fp.n1 == 4 && c.fused_fine) {
+        prof_begin(c.prof, K_MR_FINE, c.stream);
+        hipLaunchKernelGGL(k_mr_fused<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout,
+                           fc, fp, c.mech, c.err);
+        prof_end(c.prof, K_MR_FINE, c.stream);
+        return;
+      }
+    }
     prof_begin(c.prof, K_MR_SRC, c.stream);
     if (fp.nq == 4)
       hipLaunchKernelGGL((k_mr_src<NS, 4>), grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, fc, fp, A,

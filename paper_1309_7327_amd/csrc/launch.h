@@ -40,6 +40,7 @@ struct LaunchCtx {
   bool smc_stencil;   // the default narrow-stencil parameters: compile-time B
   int ref_species;    // species diffusion: -1 correction velocity, else the reference species
   bool wide;          // second-derivative pairs with the wide stencil D(a D u)
+  bool fused_fine;    // multirate fine sub-steps in one kernel where it applies
 };
 
 struct Ops {

@@ -96,6 +96,7 @@ struct ResidArgs {
 struct FineCoef {
   double S21[NSDC_MAXFINE][8];
   double S22[NSDC_MAXFINE][9];   // row q over the nodes jlo[q] .. jlo[q] + nfine - 1 of its piece
+  double S22n[4][5];   // four sub-steps: row q over all five fine nodes of the interval, zero outside its piece
   double dtq[NSDC_MAXFINE];
   int jlo[NSDC_MAXFINE];
   int n1;          // coarse nodes M1 + 1
@@ -117,5 +118,6 @@ struct FinePtrs {
   int q0_known;    // f2 at the first fine node is the step-start value F2old[0]
   int eval_last;   // evaluate and store f2 at the interval's last fine node
   int nq;          // fine sub-steps of the interval (the same as the coefficient table's)
+  int n1;          // coarse nodes (the same as the coefficient table's)
   double dt;
 };

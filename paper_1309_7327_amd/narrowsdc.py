@@ -67,6 +67,7 @@ _SIGS = {
     "set_reference_species": [_vp, _ip],
     "sdc_set_residual_exit": [_vp, ctypes.c_double],
     "set_wide_stencil": [_vp, _ip],
+    "sdc_set_fused_fine": [_vp, _ip],
     "sdc_residual_history": [_vp, _ip, _vp, _vp, _vp],
     "sdc_vjp_workspace_size": [_vp, ctypes.POINTER(BoxDesc), ctypes.POINTER(Scheme), _ip,
                                ctypes.POINTER(ctypes.c_size_t)],
@@ -212,6 +213,11 @@ class Context:
         """Second derivatives with the wide stencil D(a D u) (Section 2.2)
         instead of the narrow one."""
         self._check(_lib.set_wide_stencil(self.h, 1 if enable else 0))
+
+    def set_fused_fine(self, enable=True):
+        """Multirate fine sub-steps in one kernel where the scheme and
+        mechanism allow it (results are identical either way)."""
+        self._check(_lib.sdc_set_fused_fine(self.h, 1 if enable else 0))
 
     def set_residual_exit(self, ratio=0.0):
         """0: K sweeps per step; ratio > 1: skip a step's remaining sweeps once

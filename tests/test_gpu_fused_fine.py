@@ -1,0 +1,71 @@
+"""Fine sub-steps of the multirate sweep (eq. mrupdate): the one-kernel form
+(quadrature increments kept in registers) against the two-kernel form
+(streaming quadrature pass, then the sub-step kernel), through the C-ABI.
+Both evaluate the same expressions in the same order, so the states after
+whole multirate steps must agree bit for bit; the kernel profile shows
+which form ran.  Parity of either form with the oracle is covered by the
+multirate step tests of the parity suite, which run the default form."""
+import pytest
+
+from synth import fields, mechanism
+from synth.workloads import make_primitives, time_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1309_7327_amd import narrowsdc as N  # noqa: E402
+import gpu_util as G  # noqa: E402
+
+
+def _run(kind, prim, dx, sch, nsteps, dt, fused):
+    m = mechanism.load(kind)
+    ctx = N.Context(0)
+    ctx.set_mechanism(m)
+    ctx.set_fused_fine(fused)
+    bx, U = G.device_state(ctx, prim, dx)
+    ws, nb = N.workspace(ctx, [bx], sch)
+    ctx.profile(True)
+    ctx.sdc_step(bx, U, dt, nsteps, sch, ws, nb)
+    ctx.check_status()
+    prof = ctx.profile_read()
+    ctx.close()
+    return U, prof
+
+
+@pytest.mark.parametrize("kind,shape,sch,nsteps", [
+    ("mech9", (7, 9, 70), (4, 3, 5, 1), 2),     # GL4 / GL5 type (b); x tile plus a ragged tail
+    ("mech9le", (12, 10, 6), (4, 2, 3, 2), 1),  # GL3 repeated twice per coarse interval (type c)
+    ("mech21", (5, 6, 9), (4, 2, 5, 1), 1),     # 21 species: the two-kernel form either way
+    ("mech9", (6, 5, 7), (3, 2, 5, 1), 1),      # three coarse nodes: the two-kernel form either way
+])
+def test_fused_fine_equals_two_kernel_form(kind, shape, sch, nsteps):
+    m = mechanism.load(kind)
+    prim = fields.sines(shape, 1e-4, m["ns"], 31)
+    s = N.scheme(*sch)
+    dt = time_step("box16_sdc")
+    Uf, pf = _run(kind, prim, 1e-4, s, nsteps, dt, True)
+    Us, ps = _run(kind, prim, 1e-4, s, nsteps, dt, False)
+    applies = m["ns"] <= 9 and sch[0] == 4 and (sch[2] - 1) * sch[3] == 4
+    print(kind, shape, sch, "one-kernel form applies:", applies, {k: v[1] for k, v in pf.items()})
+    assert ("mr_src" not in pf) == applies
+    assert "mr_src" in ps and "mr_fine" in pf and "mr_fine" in ps
+    assert torch.equal(Uf, Us), float((Uf - Us).abs().max())
+
+
+def test_fused_fine_equals_two_kernel_form_at_full_size():
+    """The 128^3, 9-species headline box, one multirate step."""
+    m = mechanism.load("mech9")
+    prim = make_primitives("box128_mrsdc", m)
+    s = N.scheme(4, 6, 5, 1)
+    dt = time_step("box128_mrsdc")
+    Uf, pf = _run("mech9", prim, 1e-4, s, 1, dt, True)
+    Us, ps = _run("mech9", prim, 1e-4, s, 1, dt, False)
+    assert "mr_src" not in pf and "mr_src" in ps
+    same = torch.equal(Uf, Us)
+    diff = float((Uf - Us).abs().max())
+    del Uf, Us
+    torch.cuda.empty_cache()
+    assert same, diff
