@@ -303,8 +303,20 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
         return acc[5 + k];
     };
     auto line = [&](const double *f, double *v) {
+      if constexpr (D == 0) {
 #pragma unroll
-      for (int o = 0; o < 9; ++o) v[o] = (f + (o - 4) * st)[s];
+        for (int o = 0; o < 9; ++o) v[o] = (f + (o - 4) * st)[s];
+      } else {
+        // strided taps as buffer loads: the lane offset is shared by the nine
+        // taps and each tap's stride multiple rides in the scalar offset
+        // (global loads would need a 64-bit address per tap); the range,
+        // [f - 4 st, f + nS), holds every tap of every interior cell
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(f - 4 * st), (short)0, (unsigned)((nS + 4 * st) * 8), 0x00020000);
+#pragma unroll
+        for (int o = 0; o < 9; ++o)
+          v[o] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(s * 8u), (int)(o * st * 8), 0));
+      }
     };
     // wide stencil: 17 samples along D (periodic images past the ghost
     // layers), and v_o = w_o (D u)_o / idx with w the first-derivative
