@@ -427,10 +427,14 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
 void eval_rhs_g(const Ops *o, const LaunchCtx &l, FRef U, double *P, double *G, FRef F, unsigned parts,
                 bool warm = false) {
   o->ghost(l, U);
-  o->prims(l, U, P, F, (parts & RHS_REACT) ? 2 : 1, warm ? 1 : 0);
+  // with the chemistry on, the primitives kernel writes F (zeros and the
+  // source) and the direction passes add to it; without, the x pass stores
+  // into F (bit 8) and nothing clears it first
+  const bool react = parts & RHS_REACT, ad = parts & RHS_AD;
+  o->prims(l, U, P, F, react ? 2 : (ad ? 0 : 1), warm ? 1 : 0);
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
-  if (parts & RHS_AD) {
-    for (int d = 0; d < 3; ++d) o->dir(l, d, U, P, G, F, parts & RHS_AD);
+  if (ad) {
+    for (int d = 0; d < 3; ++d) o->dir(l, d, U, P, G, F, (parts & RHS_AD) | (d == 0 && !react ? 8u : 0u));
   }
 }
 

@@ -251,6 +251,9 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
 // WIDE: the second-derivative pairs with the wide stencil D(a D u) of two
 // eighth-order first derivatives (Section 2.2) instead of the narrow one;
 // its u samples reach 8 cells along D, taken from the periodic images.
+// parts: bit 1 the convective terms, bit 2 the diffusive terms, bit 8 store
+// the pass's sums into F instead of adding them (the first pass of an
+// evaluation that nothing wrote to before).
 template <int NS, int D, bool FIXED, bool REF, bool WIDE>
 __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
@@ -643,14 +646,28 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
         }
       }
     }
-    if constexpr (ACC_LDS) {
+    // the first pass of an evaluation that nothing wrote to before (bit 8
+    // of parts) stores its sums; every other pass adds to what is there
+    if (parts & 8) {
+      if constexpr (ACC_LDS) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) (F + q * nI)[i] += acc[q];
+        for (int q = 0; q < 5; ++q) (F + q * nI)[i] = acc[q];
 #pragma unroll 1
-      for (int k = 0; k < NS; ++k) (F + (5 + k) * nI)[i] += spc(k);
-    } else {
+        for (int k = 0; k < NS; ++k) (F + (5 + k) * nI)[i] = spc(k);
+      } else {
 #pragma unroll
-      for (int q = 0; q < NU; ++q) (F + q * nI)[i] += acc[q];
+        for (int q = 0; q < NU; ++q) (F + q * nI)[i] = acc[q];
+      }
+    } else {
+      if constexpr (ACC_LDS) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) (F + q * nI)[i] += acc[q];
+#pragma unroll 1
+        for (int k = 0; k < NS; ++k) (F + (5 + k) * nI)[i] += spc(k);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NU; ++q) (F + q * nI)[i] += acc[q];
+      }
     }
   }
 }
