@@ -59,8 +59,11 @@ def work_model(ns, nr, n_coarse, n_fine_per_interval, fused=False):
         # interval's f1 and f2 node values, write U and the new f2 values
         step_flops += src_flops
         step_bytes = 8 * (2 * nu + nu * (n1 + 1) + ns * (r + 1) + r * ns)
+    # in evaluations without the chemistry (the multirate coarse component)
+    # the x pass stores dU/dt without reading it first
+    dir_x_bytes = dir_bytes - (8 * nu if r else 0)
     return {
-        "dir_x": (dir_flops, dir_bytes), "dir_y": (dir_flops, dir_bytes), "dir_z": (dir_flops, dir_bytes),
+        "dir_x": (dir_flops, dir_x_bytes), "dir_y": (dir_flops, dir_bytes), "dir_z": (dir_flops, dir_bytes),
         "mr_fine": (step_flops, step_bytes), "mr_src": (src_flops, src_bytes),
         "prims": (newton + 40 * ns, 8 * (nu + np_)),
     }
