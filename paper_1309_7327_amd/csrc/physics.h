@@ -179,7 +179,7 @@ __device__ void production_sh(const DevMech *__restrict__ m, double rho, double 
   sh[2 * A + NS * S] = 0.0;
   const double lnRTp = lnT + LN_RU_PREF;
   const int nr = m->nr;
-#pragma unroll 2
+#pragma unroll 4
   for (int j = 0; j < nr; ++j) {
     const int r0 = m->rs[j][0] * S, r1 = m->rs[j][1] * S, p0 = m->ps[j][0] * S, p1 = m->ps[j][1] * S;
     const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
