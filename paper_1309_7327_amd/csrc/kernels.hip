@@ -953,6 +953,144 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
   }
 }
 
+// Orders the LDS accesses of the lanes of one wave (the two lanes that share
+// a cell in k_mr_pair are in one wave; a wave executes its LDS
+// instructions in issue order, so only the compiler must not move them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// k_mr_step with two lanes per cell, for more than nine species.  A cell's
+// chemistry arrays (concentrations, Gibbs energies, production: 3 (Ns+1)
+// doubles, 528 bytes at 21 species) in LDS allowed one wave per SIMD with a
+// lane per cell; two lanes sharing a cell's column halve the LDS per lane, so
+// two waves per SIMD fit.  Both lanes of a pair run the cell's state update,
+// Newton solve and species setup (redundantly, same values), then each takes
+// every other reaction (its coefficients from an LDS copy of the mechanism's
+// reaction table, the lanes now being on different reactions) and adds its
+// rates into the shared production array with LDS atomics; each lane writes
+// half of the outputs.  A workgroup's lanes (whole waves, at most 256) cover
+// the cells of a work item in two passes of half as many.
+template <int NS>
+__global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ boxes,
+                                                    const Item *__restrict__ items, int nitems,
+                                                    TileShape ts, FRef Uin, FRef Uout,
+                                                    const FineCoef *__restrict__ fc, FinePtrs fp,
+                                                    const double *__restrict__ Abase, long long aslot,
+                                                    const DevMech *__restrict__ m, int *err) {
+  constexpr int NU = 5 + NS, CS = 128, A = (NS + 1) * CS;
+  __shared__ double col[3 * A];
+  __shared__ double tab[64];
+  __shared__ int rsp[NSDC_NRMAX][4];       // reactant and product slots, times CS
+  __shared__ double rco[NSDC_NRMAX][4];    // ln A, beta, Ea/R, sum of nu
+  const int nr = m->nr;
+  for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = m->e2tab[j];
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    rsp[j][0] = m->rs[j][0] * CS;
+    rsp[j][1] = m->rs[j][1] * CS;
+    rsp[j][2] = m->ps[j][0] * CS;
+    rsp[j][3] = m->ps[j][1] * CS;
+    rco[j][0] = m->lnA[j];
+    rco[j][1] = m->beta[j];
+    rco[j][2] = m->EaR[j];
+    rco[j][3] = (double)m->dnu[j];
+  }
+  __syncthreads();
+  // lane l of wave v: cell slot 32 v + (l mod 32), reaction parity l / 32 (the
+  // two lanes of a cell 32 apart in one wave, so each group of sixteen lanes
+  // that the LDS serves together works on one species of sixteen neighbouring
+  // cells: consecutive doubles, no bank conflicts)
+  const int lane = threadIdx.x & 63, slot = (threadIdx.x >> 6) * 32 + (lane & 31), sub = lane >> 5;
+  double *sh = col + slot;
+  // the chemistry source of one cell, rates split between the two lanes
+  auto production_pair = [&](double rho, double T, const double *Y, double *wdot) {
+    const double lnT = log(T), invT = 1.0 / T;
+    wave_sync();   // the previous sub-step's reads of this column are done
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      sh[k * CS] = rho * Y[k] * m->invW[k];
+      sh[A + k * CS] = g_RT(m, k, T, invT, lnT);
+      sh[2 * A + k * CS] = 0.0;
+    }
+    sh[NS * CS] = 1.0;
+    sh[A + NS * CS] = 0.0;
+    sh[2 * A + NS * CS] = 0.0;
+    wave_sync();
+    const double lnRTp = lnT + LN_RU_PREF;
+#pragma unroll 4
+    for (int j = sub; j < nr; j += 2) {
+      const int r0 = rsp[j][0], r1 = rsp[j][1], p0 = rsp[j][2], p1 = rsp[j][3];
+      const double lnkf = rco[j][0] + rco[j][1] * lnT - rco[j][2] * invT;
+      const double dg = (sh[A + p0] + sh[A + p1]) - (sh[A + r0] + sh[A + r1]);
+      const double kf = exp_tab(lnkf, tab);
+      const double kr = exp_tab(lnkf + dg + rco[j][3] * lnRTp, tab);
+      const double q = kf * sh[r0] * sh[r1] - kr * sh[p0] * sh[p1];
+      atomicAdd(sh + 2 * A + r0, -q);
+      atomicAdd(sh + 2 * A + r1, -q);
+      atomicAdd(sh + 2 * A + p0, q);
+      atomicAdd(sh + 2 * A + p1, q);
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < NS; ++k) wdot[k] = sh[2 * A + k * CS] * m->W[k];
+  };
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+    const long long o1 = b.offI * NU, o2 = b.offI * NS;
+    const double *Ui = Uin.get(w.box, b.offS * NU);
+    double *Uo = Uout.get(w.box, b.offS * NU);
+    auto F2 = [&](int slot, int k) { return fp.F2base + (slot * fp.f2slot + o2 + k * nI); };
+    auto Af = [&](int r, int q) { return Abase + (r * aslot + o1 + q * nI); };
+    for (int h = 0; h < 2; ++h) {
+      const int cell = h * (int)(blockDim.x >> 1) + slot;
+      const int x = w.x0 + cell % ts.tx, y = w.y0 + (cell / ts.tx) % ts.ty, z = w.z0 + cell / (ts.tx * ts.ty);
+      if (cell >= ts.tx * ts.ty * ts.tz || x >= b.nx || y >= b.ny || z >= b.nz) continue;
+      const unsigned s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+      const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
+      double Uc[NU];
+#pragma unroll
+      for (int q = 0; q < NU; ++q) Uc[q] = (Ui + q * nS)[s];
+      const int nq = fc->nq;
+      int errs = 0;
+      double Tprev = 1000.0;
+      for (int qq = 0; qq < nq; ++qq) {
+        double f2[NS];
+        if (qq == 0 && fp.q0_known) {
+#pragma unroll
+          for (int k = 0; k < NS; ++k) f2[k] = F2(fp.F2old[0], k)[i];
+        } else {
+          double rho, u[3], Y[NS], T;
+          errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
+          Tprev = T;
+          production_pair(rho, T, Y, f2);
+#pragma unroll
+          for (int k = 0; k < NS; ++k)
+            if ((k & 1) == sub) F2(fp.F2new[qq], k)[i] = f2[k];
+        }
+        const double dtq = fc->dtq[qq] * fp.dt;
+#pragma unroll
+        for (int q = 0; q < NU; ++q) Uc[q] += Af(qq, q)[i] + (q >= 5 ? dtq * f2[q - 5] : 0.0);
+      }
+      if (fp.eval_last) {
+        double rho, u[3], Y[NS], T, f2[NS];
+        errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
+        production_pair(rho, T, Y, f2);
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+          if ((k & 1) == sub) F2(fp.F2new[nq], k)[i] = f2[k];
+      }
+      if (errs) atomicOr(err, errs);
+#pragma unroll
+      for (int q = 0; q < NU; ++q)
+        if ((q & 1) == sub) (Uo + q * nS)[s] = Uc[q];
+    }
+  }
+}
+
 // The two kernels above fused for four coarse nodes, four fine sub-steps
 // and at most nine species: the interval's increments are formed in registers with k_mr_src's
 // arithmetic and consumed by k_mr_step's sub-steps without the round trip
@@ -1219,8 +1357,16 @@ struct Launch {
                          aslot);
     prof_end(c.prof, K_MR_SRC, c.stream);
     prof_begin(c.prof, K_MR_FINE, c.stream);
-    hipLaunchKernelGGL(k_mr_step<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
-                       fp, A, aslot, c.mech, c.err);
+    bool pair = false;
+    if constexpr (NS > 9) {
+      pair = block.x % 64 == 0 && block.x <= 256;
+      if (pair)
+        hipLaunchKernelGGL(k_mr_pair<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
+                           fp, A, aslot, c.mech, c.err);
+    }
+    if (!pair)
+      hipLaunchKernelGGL(k_mr_step<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
+                         fp, A, aslot, c.mech, c.err);
     prof_end(c.prof, K_MR_FINE, c.stream);
   }
 };
