@@ -1357,14 +1357,12 @@ struct Launch {
                          aslot);
     prof_end(c.prof, K_MR_SRC, c.stream);
     prof_begin(c.prof, K_MR_FINE, c.stream);
-    bool pair = false;
-    if constexpr (NS > 9) {
-      pair = block.x % 64 == 0 && block.x <= 256;
-      if (pair)
-        hipLaunchKernelGGL(k_mr_pair<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
-                           fp, A, aslot, c.mech, c.err);
-    }
-    if (!pair)
+    // (interior tiles are whole waves, at most 256 threads, as k_mr_pair needs:
+    // sdc_set_tiles and the tile choices of the library keep them so)
+    if constexpr (NS > 9)
+      hipLaunchKernelGGL(k_mr_pair<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
+                         fp, A, aslot, c.mech, c.err);
+    else
       hipLaunchKernelGGL(k_mr_step<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
                          fp, A, aslot, c.mech, c.err);
     prof_end(c.prof, K_MR_FINE, c.stream);
