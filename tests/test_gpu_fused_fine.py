@@ -69,3 +69,49 @@ def test_fused_fine_equals_two_kernel_form_at_full_size():
     del Uf, Us
     torch.cuda.empty_cache()
     assert same, diff
+
+
+def test_two_lanes_per_cell_with_an_odd_reaction_count():
+    """Above nine species the fine sub-steps split a cell's reactions between
+    two lanes (every other reaction each); with an odd count one lane takes one
+    more.  83 of the 21-species mechanism's 84 reactions, one multirate step on
+    a ragged box, against the oracle."""
+    import numpy as np
+    import oracle
+    from oracle import sdc as osdc
+
+    m = dict(mechanism.load("mech21"))
+    keep = 83
+    for k in ("A", "b", "Ea", "nu_f", "nu_r"):
+        m[k] = np.ascontiguousarray(m[k][:keep])
+    m["nr"] = keep
+    om = oracle.Mechanism(m)
+    ctx = N.Context(0)
+    ctx.set_mechanism(m)
+    shape = (5, 6, 7)
+    prim = fields.sines(shape, 1e-4, m["ns"], 17)
+    bx, U = G.device_state(ctx, prim, 1e-4)
+    U0g = G.interior(G.host(U)).copy()
+    dt = time_step("box16_sdc")
+    s = N.scheme(4, 2, 5, 1)
+    ws, nb = N.workspace(ctx, [bx], s)
+    ctx.profile(True)
+    ctx.sdc_step(bx, U, dt, 1, s, ws, nb)
+    ctx.check_status()
+    assert "mr_fine" in ctx.profile_read()
+    Ug = G.interior(G.host(U))
+    ctx.close()
+    U0 = oracle.prim_to_cons(om, prim)
+
+    def step(V, pt):
+        f1 = lambda W, t: oracle.rhs(om, W, 1e-4, parts=oracle.AD)
+        f2 = lambda W, t: oracle.rhs(om, W, 1e-4, parts=oracle.REACT)
+        t1, t2, pieces = osdc.mr_nodes(4, 5, 1)
+        return osdc.mrsdc_run(f1, f2, V, 0.0, dt, t1, t2, pieces, 2, 1, pt)
+
+    ref, floor, dfloor = G.ulp_floor_step(step, U0)
+    ok, rep = G.compare(Ug, ref, floor)
+    okd, repd = G.compare(Ug - U0g, ref - U0, dfloor, state=ref)
+    print("U ", G.fmt(rep))
+    print("dU", G.fmt(repd))
+    assert ok and okd, G.fmt(repd)
