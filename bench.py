@@ -1,20 +1,24 @@
 """Benchmark: multirate SDC steps of the reacting Navier-Stokes right-hand side
 on one MI355X (FP64), with the oracle timed on the host cores as a baseline.
 
-Default workload: 128^3 periodic box, 9 species / 21 reactions, turbulent
-velocity (k^-5/3, u_rms 5 m/s) and a planar two-front flame slab, MRSDC mode
-1 with advection-diffusion on 4 Gauss-Lobatto nodes and chemistry on 5
+Default workload: the largest single-box case, a 256^3 periodic box with 21
+species / 84 reactions, turbulent velocity (k^-5/3 on shells 1..32, u_rms
+5 m/s) and a planar two-front flame slab, MRSDC mode 1 with
+advection-diffusion on 4 Gauss-Lobatto nodes and chemistry on 5
 Gauss-Lobatto nodes per coarse interval, 6 sweeps.  One "step" is one MRSDC
-time step of the whole box.
+time step of the whole box.  The line also carries the 128^3, 9-species
+case's figures (same scheme) under "box128_mrsdc".
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                   [--no-cpu-baseline]
 
-Prints one JSON line.  value = SDC steps/s (inputs resident in HBM); the
-line also carries Mcell advection-diffusion and reaction evaluations per
-second, the roofline of the dominant kernel (average duration from HIP
-events recorded on the launch stream over the timed region) and the oracle
-baseline.
+Prints one JSON line.  value = SDC steps/s (inputs resident in HBM) over the
+timed region of exactly K steps; the line also carries Mcell
+advection-diffusion and reaction evaluations per second, the roofline of the
+dominant kernel and of the three stencil direction passes together (average
+durations from HIP events recorded on the launch stream around every launch
+of the timed region), the same K steps timed again with no events attached
+(unprofiled_ms_per_step), and the oracle baseline.
 """
 import argparse
 import json
@@ -92,7 +96,8 @@ def cpu_baseline(workload, mech, n_cells_full):
     from synth.workloads import WORKLOADS, make_primitives, time_step
     wl = WORKLOADS[workload]
     om = oracle.Mechanism(mech, ref_species=wl.get("ref_species", -1), wide=wl.get("wide", False))
-    edge = 64
+    # about 10-30 s of host work: a 64^3 box with 9 species, 48^3 with 21
+    edge = 64 if mech["ns"] <= 9 else 48
     prim = make_primitives(workload, mech, shape_override=(edge,) * 3)
     U0 = oracle.prim_to_cons(om, prim)
     dt = time_step(workload)
@@ -332,13 +337,160 @@ def copy_ceiling(torch, reps=5):
     return 2.0 * (1 << 30) / (best * 1e-3) / 1e9
 
 
+def roofline_of(model, name, dur_ms, units):
+    """Roofline entry of kernel kind `name` from its per-unit work model and
+    average launch duration: "hbm" below the ridge, else "alu"."""
+    fl, by = model[name]
+    flops, bytes_ = fl * units, by * units
+    if flops / bytes_ * HBM_PEAK_GBS * 1e9 < FP64_PEAK_TFLOPS * 1e12:
+        roof = {"bound": "hbm", "achieved": bytes_ / (dur_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops / (dur_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["fp64_tflops"] = flops / (dur_ms * 1e-3) / 1e12
+    roof["hbm_gbs"] = bytes_ / (dur_ms * 1e-3) / 1e9
+    return roof
+
+
+def run_box(args, workload, steps, warmup, with_baseline):
+    """Warm-up, then exactly `steps` SDC steps of one box timed with HIP
+    events around every launch, then the same number of steps again with no
+    events attached.  Returns the result fields of the JSON line."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    from paper_1309_7327_amd import narrowsdc as N
+    from synth import mechanism
+    from synth.workloads import WORKLOADS, make_primitives, time_step
+
+    wl = WORKLOADS[workload]
+    mech = mechanism.load(wl["mech"])
+    ns = mech["ns"]
+    nz, ny, nx = wl["shape"]
+    ncell = nx * ny * nz
+    dx = wl["dx"]
+    dt = time_step(workload)
+    sch_d = wl["scheme"]
+    if sch_d["kind"] == "sdc":
+        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], 0, 1)
+        r = 0
+    else:
+        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], sch_d["n_fine"], sch_d["fine_repeat"])
+        r = (sch_d["n_fine"] - 1) * sch_d["fine_repeat"]
+
+    ctx = N.Context(0)
+    ctx.set_mechanism(mech)
+    ctx.set_reference_species(wl.get("ref_species", -1))
+    ctx.set_residual_exit(wl.get("residual_ratio", 0.0))
+    ctx.set_wide_stencil(wl.get("wide", False))
+    prim = make_primitives(workload, mech)
+    bx = N.box(nx, ny, nz, dx)
+    U = torch.zeros(N.ghosted_shape(5 + ns, nz, ny, nx), dtype=torch.float64, device="cuda")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    ctx.prim_to_cons(bx, dev(prim["p"]), dev(prim["T"]), dev(prim["Y"]), dev(prim["u"]), U)
+    del prim
+    ws, nb = N.workspace(ctx, [bx], sch)
+    stream = torch.cuda.current_stream()
+
+    if warmup > 0:
+        ctx.sdc_step(bx, U, dt, warmup, sch, ws, nb)
+    ctx.check_status()
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` steps, per-launch HIP events on the
+    # launch stream (their durations give the roofline entries)
+    lib = N._lib
+    lib.sdc_profile_enable(ctx.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sdc_step(bx, U, dt, steps, sch, ws, nb)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check_status()
+    _, sweeps_done = ctx.residual_history()
+    tot = (ctypes.c_double * 32)()
+    cnt = (ctypes.c_int * 32)()
+    nk = lib.sdc_profile_read(ctx.h, ctypes.c_void_p(stream.cuda_stream), tot, cnt)
+    kern = {lib.sdc_kernel_name(i).decode(): (tot[i], cnt[i]) for i in range(nk) if cnt[i] > 0}
+    lib.sdc_profile_enable(ctx.h, 0)
+    # the same number of steps with no events attached
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.sdc_step(bx, U, dt, steps, sch, ws, nb)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ctx.check_status()
+
+    el = t1 - t0
+    steps_per_s = steps / el
+    M1 = sch_d["n_coarse"] - 1
+    # with the residual early exit the sweeps taken replace K per step
+    n_ad = (sweeps_done if wl.get("residual_ratio") else steps * sch_d["sweeps"]) * M1
+    n_r = n_ad * r if r else n_ad
+    # the one-kernel fine sub-steps run for four coarse nodes, four fine
+    # sub-steps per interval and at most nine species
+    fused = ns <= 9 and sch_d["n_coarse"] == 4 and r == 4
+    model = work_model(ns, mech["nr"], sch_d["n_coarse"], r, fused)
+    dominant = max(kern, key=lambda k: kern[k][0])
+    dur_ms = kern[dominant][0] / kern[dominant][1]
+    if dominant in model:
+        roof = roofline_of(model, dominant, dur_ms, ncell)
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None}
+    roof["kernel"] = dominant
+    roof["avg_launch_ms"] = dur_ms
+    roof["traffic"] = stored_traffic(dominant, workload)
+    # the stencil pass: the three direction kernels of one advection-diffusion
+    # evaluation together
+    stencil = None
+    if all(k in kern for k in ("dir_x", "dir_y", "dir_z")):
+        dms = sum(kern[k][0] / kern[k][1] for k in ("dir_x", "dir_y", "dir_z"))
+        sfl = sum(model[k][0] for k in ("dir_x", "dir_y", "dir_z"))
+        sby = sum(model[k][1] for k in ("dir_x", "dir_y", "dir_z"))
+        stencil = {"kernels": "dir_x+dir_y+dir_z", "ms_per_evaluation": dms,
+                   "fp64_tflops": sfl * ncell / (dms * 1e-3) / 1e12,
+                   "hbm_gbs": sby * ncell / (dms * 1e-3) / 1e9}
+        stencil["bound"] = "alu" if sfl / sby * HBM_PEAK_GBS * 1e9 >= FP64_PEAK_TFLOPS * 1e12 else "hbm"
+        stencil["frac"] = (stencil["fp64_tflops"] / FP64_PEAK_TFLOPS if stencil["bound"] == "alu"
+                           else stencil["hbm_gbs"] / HBM_PEAK_GBS)
+    out = {
+        "value": steps_per_s,
+        "ms_per_step": 1e3 * el / steps,
+        "unprofiled_ms_per_step": 1e3 * (t3 - t2) / steps,
+        "config": {"workload": workload, "cells": ncell, "species": ns, "reactions": int(mech["nr"]),
+                   "scheme": sch_d, "dt": dt,
+                   "second_derivatives": "wide stencil D(a D u)" if wl.get("wide") else "narrow stencil",
+                   "species_diffusion":
+                   ("reference species %d" % wl["ref_species"]) if wl.get("ref_species", -1) >= 0
+                   else "correction velocity"},
+        "mcell_ad_evals_per_s": ncell * n_ad / el / 1e6,
+        "mcell_r_evals_per_s": ncell * n_r / el / 1e6,
+        "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},
+        "roofline": roof,
+        "stencil_roofline": stencil,
+    }
+    if wl.get("residual_ratio"):
+        out["sweeps_per_step"] = sweeps_done / steps
+    ctx.close()
+    del U, ws
+    torch.cuda.empty_cache()
+    if with_baseline:
+        out["cpu_baseline"] = cpu_baseline(workload, mech, ncell)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="box128_mrsdc")
+    ap.add_argument("--workload", default="box256_mrsdc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 128^3 figures carried beside the default workload's")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -347,11 +499,9 @@ def main():
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_1309_7327_amd import narrowsdc as N
-    from synth import mechanism
-    from synth.workloads import WORKLOADS, make_primitives, time_step
+    from paper_1309_7327_amd import narrowsdc as N  # noqa: F401  (fails loudly if unbuilt)
+    from synth.workloads import WORKLOADS
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
@@ -367,117 +517,31 @@ def main():
         return bench_batch(args)
     if args.workload == "box64_adjoint":
         return bench_adjoint(args)
-    mech = mechanism.load(wl["mech"])
-    ns = mech["ns"]
-    nz, ny, nx = wl["shape"]
-    ncell = nx * ny * nz
-    dx = wl["dx"]
-    dt = time_step(args.workload)
-    sch_d = wl["scheme"]
-    if sch_d["kind"] == "sdc":
-        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], 0, 1)
-        r = 0
-    else:
-        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], sch_d["n_fine"], sch_d["fine_repeat"])
-        r = (sch_d["n_fine"] - 1) * sch_d["fine_repeat"]
-
-    ctx = N.Context(0)
-    ctx.set_mechanism(mech)
-    ctx.set_reference_species(wl.get("ref_species", -1))
-    ctx.set_residual_exit(wl.get("residual_ratio", 0.0))
-    ctx.set_wide_stencil(wl.get("wide", False))
-    prim = make_primitives(args.workload, mech)
-    bx = N.box(nx, ny, nz, dx)
-    U = torch.zeros(N.ghosted_shape(5 + ns, nz, ny, nx), dtype=torch.float64, device="cuda")
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-    ctx.prim_to_cons(bx, dev(prim["p"]), dev(prim["T"]), dev(prim["Y"]), dev(prim["u"]), U)
-    del prim
-    ws, nb = N.workspace(ctx, [bx], sch)
-    stream = torch.cuda.current_stream()
-
-    if args.warmup > 0:
-        ctx.sdc_step(bx, U, dt, args.warmup, sch, ws, nb)
-    ctx.check_status()
-    torch.cuda.synchronize()
-
-    lib = N._lib
-    lib.sdc_profile_enable(ctx.h, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.sdc_step(bx, U, dt, args.steps, sch, ws, nb)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.check_status()
-    _, sweeps_done = ctx.residual_history()
-    import ctypes
-    tot = (ctypes.c_double * 32)()
-    cnt = (ctypes.c_int * 32)()
-    nk = lib.sdc_profile_read(ctx.h, ctypes.c_void_p(stream.cuda_stream), tot, cnt)
-    lib.sdc_kernel_name.restype = ctypes.c_char_p
-    lib.sdc_kernel_name.argtypes = [ctypes.c_int]
-    kern = {lib.sdc_kernel_name(i).decode(): (tot[i], cnt[i]) for i in range(nk) if cnt[i] > 0}
-    lib.sdc_profile_enable(ctx.h, 0)
-
-    el = t1 - t0
-    steps_per_s = args.steps / el
-    M1 = sch_d["n_coarse"] - 1
-    # with the residual early exit the sweeps taken replace K per step
-    n_ad = (sweeps_done if wl.get("residual_ratio") else args.steps * sch_d["sweeps"]) * M1
-    n_r = n_ad * r if r else n_ad
-    # the one-kernel fine sub-steps run for four coarse nodes, four fine
-    # sub-steps per interval and at most nine species
-    fused = ns <= 9 and sch_d["n_coarse"] == 4 and r == 4
-    model = work_model(ns, mech["nr"], sch_d["n_coarse"], r, fused)
-    dominant = max(kern, key=lambda k: kern[k][0])
-    dur_ms = kern[dominant][0] / kern[dominant][1]
-    if dominant in model:
-        fl, by = model[dominant]
-        units = ncell
-        flops = fl * units
-        bytes_ = by * units
-        ai = flops / bytes_
-        if ai * HBM_PEAK_GBS * 1e9 < FP64_PEAK_TFLOPS * 1e12:
-            roof = {"bound": "hbm", "achieved": bytes_ / (dur_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s"}
-        else:
-            roof = {"bound": "alu", "achieved": flops / (dur_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s"}
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    else:
-        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None}
-    roof["kernel"] = dominant
-    roof["avg_launch_ms"] = dur_ms
-    roof["traffic"] = stored_traffic(dominant, args.workload)
-
+    res = run_box(args, args.workload, args.steps, args.warmup, not args.no_cpu_baseline)
     out = {
         "metric": "Mcell-RHS evals/s + SDC steps/s (FP64, 1 MI355X); achieved HBM GB/s vs peak",
-        "value": steps_per_s,
+        "value": res.pop("value"),
         "unit": "SDC steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * el / args.steps,
+        "ms_per_step": res.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "cells": ncell, "species": ns, "reactions": int(mech["nr"]),
-                   "scheme": sch_d, "dt": dt,
-                   "second_derivatives": "wide stencil D(a D u)" if wl.get("wide") else "narrow stencil",
-                   "species_diffusion":
-                   ("reference species %d" % wl["ref_species"]) if wl.get("ref_species", -1) >= 0
-                   else "correction velocity"},
-        "mcell_ad_evals_per_s": ncell * n_ad / el / 1e6,
-        "mcell_r_evals_per_s": ncell * n_r / el / 1e6,
-        "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},
-        "roofline": roof,
-        "hbm_copy_gbs": args.copy_gbs,
+        "config": res.pop("config"),
     }
-    if wl.get("residual_ratio"):
-        out["sweeps_per_step"] = sweeps_done / args.steps
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, mech, ncell)
+    out.update(res)
+    out["hbm_copy_gbs"] = args.copy_gbs
+    if args.workload == "box256_mrsdc" and not args.no_extra:
+        # the 128^3, 9-species case of the same scheme, as extra keys
+        ex = run_box(args, "box128_mrsdc", 10, 1, False)
+        out["box128_mrsdc"] = {k: ex[k] for k in ("value", "ms_per_step", "unprofiled_ms_per_step",
+                                                  "mcell_ad_evals_per_s", "mcell_r_evals_per_s",
+                                                  "kernels_ms", "roofline", "stencil_roofline")}
+        out["box128_mrsdc"]["unit"] = "SDC steps/s"
     print(json.dumps(out), flush=True)
 
 

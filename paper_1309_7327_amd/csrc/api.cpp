@@ -232,9 +232,12 @@ struct sdc_context {
   // rhs_eval scratch
   double *scratch = nullptr;
   size_t scratch_bytes = 0;
-  // multirate coefficient tables, keyed by scheme
+  // multirate coefficient tables, one per scheme (kept until the context is
+  // destroyed: captured step graphs hold their addresses); d_fine is the
+  // current scheme's
   FineCoef *d_fine = nullptr;
   std::string fine_key;
+  std::map<std::string, FineCoef *> fine_tabs;
   std::map<std::string, std::unique_ptr<Plan>> plans;
   TileShape forceI{0, 0, 0}, forceS{0, 0, 0};
   int grid_cap = 0;
@@ -264,6 +267,17 @@ namespace {
 int fail(sdc_context *c, int code, const std::string &m) {
   if (c) c->msg = m;
   return code;
+}
+
+// Captured step graphs hold device addresses (plans, coefficient tables,
+// the mechanism's kernel instances) and the kernel variants chosen at
+// capture; every change of those drops them.
+void drop_graphs(sdc_context *c) {
+  if (c->graphs.empty()) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();   // no replay may still be running
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  c->graphs.clear();
 }
 
 #define HIPCHECK(ctx, expr)                                                                 \
@@ -324,7 +338,10 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
     *out = it->second.get();
     return SDC_OK;
   }
-  if (c->plans.size() > 512) c->plans.clear();
+  if (c->plans.size() > 512) {
+    drop_graphs(c);
+    c->plans.clear();
+  }
   auto p = std::make_unique<Plan>();
   p->nbox = nbox;
   p->boxes.assign(bx, bx + nbox);
@@ -484,6 +501,12 @@ int fine_tables(sdc_context *c, const sdc_scheme *s) {
   char key[64];
   snprintf(key, sizeof key, "%d,%d,%d", s->n_coarse, s->n_fine, s->fine_repeat);
   if (c->d_fine && c->fine_key == key) return SDC_OK;
+  auto known = c->fine_tabs.find(key);
+  if (known != c->fine_tabs.end()) {
+    c->d_fine = known->second;
+    c->fine_key = key;
+    return SDC_OK;
+  }
   const int M1 = s->n_coarse - 1;
   const int r = (s->n_fine - 1) * s->fine_repeat;
   std::vector<long double> t1 = gauss_lobatto(s->n_coarse), g = gauss_lobatto(s->n_fine);
@@ -516,10 +539,11 @@ int fine_tables(sdc_context *c, const sdc_scheme *s) {
         for (int j = 0; j < s->n_fine; ++j) f.S22n[q][f.jlo[q] + j] = f.S22[q][j];
     }
   }
-  if (c->d_fine) (void)hipFree(c->d_fine);
-  c->d_fine = nullptr;
-  HIPCHECK(c, hipMalloc(&c->d_fine, sizeof(FineCoef) * M1));
-  HIPCHECK(c, hipMemcpy(c->d_fine, fc.data(), sizeof(FineCoef) * M1, hipMemcpyHostToDevice));
+  FineCoef *d = nullptr;
+  HIPCHECK(c, hipMalloc(&d, sizeof(FineCoef) * M1));
+  c->fine_tabs[key] = d;
+  HIPCHECK(c, hipMemcpy(d, fc.data(), sizeof(FineCoef) * M1, hipMemcpyHostToDevice));
+  c->d_fine = d;
   c->fine_key = key;
   return SDC_OK;
 }
@@ -739,13 +763,14 @@ int sdc_context_destroy(sdc_context *c) {
   if (!c) return SDC_EINVAL;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
-  c->graphs.clear();
+  drop_graphs(c);
   c->plans.clear();
   if (c->d_err) (void)hipFree(c->d_err);
   if (c->d_mech) (void)hipFree(c->d_mech);
   if (c->scratch) (void)hipFree(c->scratch);
-  if (c->d_fine) (void)hipFree(c->d_fine);
+  for (auto &f : c->fine_tabs) (void)hipFree(f.second);
+  c->fine_tabs.clear();
+  c->d_fine = nullptr;
   if (c->d_resid) (void)hipFree(c->d_resid);
   delete c;
   return SDC_OK;
@@ -759,6 +784,7 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
   if (!m->W || !m->nasa || !m->Le || (m->nr > 0 && (!m->A || !m->b || !m->Ea || !m->nu_f || !m->nu_r)))
     return fail(c, SDC_EINVAL, "null mechanism array");
   if (!(m->Tlo > 0) || !(m->Thi > m->Tlo)) return fail(c, SDC_EINVAL, "bad temperature range");
+  drop_graphs(c);
   DevMech &d = c->h_mech;
   std::memset(&d, 0, sizeof d);
   d.ns = m->ns;
@@ -943,17 +969,19 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
     HIPCHECK(c, hipGetLastError());
     return SDC_OK;
   }
-  char buf[256];
-  snprintf(buf, sizeof buf, "|%p|%.17g|%d|%d,%d,%d,%d|%p|%zu|%p", (void *)pl, dt, nsteps, scheme->n_coarse,
-           scheme->sweeps, scheme->n_fine, scheme->fine_repeat, workspace, ws_bytes,
-           nbox > 1 ? nullptr : (void *)U[0]);
+  // the key names everything the captured launches depend on: the plan, the
+  // scheme and its coefficient table, the state and workspace addresses and
+  // the kernel variants (species count, stencil, species-diffusion form,
+  // fine-sweep form)
+  char buf[320];
+  snprintf(buf, sizeof buf, "|%p|%.17g|%d|%d,%d,%d,%d|%p|%zu|%p|ns%d|w%d|ref%d|ff%d|smc%d|%p", (void *)pl, dt,
+           nsteps, scheme->n_coarse, scheme->sweeps, scheme->n_fine, scheme->fine_repeat, workspace, ws_bytes,
+           nbox > 1 ? nullptr : (void *)U[0], c->ops->ns, (int)c->wide, c->h_mech.ref, (int)c->fused_fine,
+           (int)c->smc_stencil, scheme->n_fine != 0 ? (void *)c->d_fine : nullptr);
   const std::string key = buf;
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
-    if (c->graphs.size() >= 8) {
-      for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
-      c->graphs.clear();
-    }
+    if (c->graphs.size() >= 8) drop_graphs(c);
     HIPCHECK(c, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     rc = run_sdc(c, pl, Uref, dt, nsteps, scheme, workspace, ws_bytes, stream);
     hipGraph_t graph = nullptr;
@@ -1011,12 +1039,14 @@ int sdc_step_batched(sdc_context *c, int nbox, const box_desc *boxes, double *co
 
 int set_wide_stencil(sdc_context *c, int enable) {
   if (!c) return SDC_EINVAL;
+  if (c->wide != (enable != 0)) drop_graphs(c);
   c->wide = enable != 0;
   return SDC_OK;
 }
 
 int sdc_set_fused_fine(sdc_context *c, int enable) {
   if (!c) return SDC_EINVAL;
+  if (c->fused_fine != (enable != 0)) drop_graphs(c);
   c->fused_fine = enable != 0;
   return SDC_OK;
 }
@@ -1044,10 +1074,7 @@ int sdc_residual_history(const sdc_context *c, int max, double *norms, int *coun
 int sdc_set_graph(sdc_context *c, int enable) {
   if (!c) return SDC_EINVAL;
   c->use_graph = enable != 0;
-  if (!enable) {
-    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
-    c->graphs.clear();
-  }
+  if (!enable) drop_graphs(c);
   return SDC_OK;
 }
 
@@ -1484,6 +1511,7 @@ int set_reference_species(sdc_context *c, int k) {
   if (!c) return SDC_EINVAL;
   if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
   if (k < -1 || k >= c->h_mech.ns) return fail(c, SDC_EINVAL, "reference species out of range");
+  if (c->h_mech.ref != k) drop_graphs(c);
   c->h_mech.ref = k;
   HIPCHECK(c, hipSetDevice(c->device));
   HIPCHECK(c, hipDeviceSynchronize());
