@@ -1,0 +1,179 @@
+"""The adjoint workload's central-difference checks: 64^3, 9 species / 21
+reactions, the vector-Jacobian product of the right-hand side (rhs_vjp) and
+the adjoint of 5 single-rate SDC steps (sdc_step_vjp), each against central
+differences of the library's own forward map on 200 seeded directions, and
+against the oracle's tangent products on some of them.
+
+Directions (seed 5000 + j): w_U ~ N(0, 1) per entry of the state, applied
+as a relative change U (1 +- h w_U); w_A ~ N(0, 1) per reaction, applied as
+A_j (1 +- h w_A,j); h = 1e-6.  The directional derivative is then
+<Ubar, U o w_U> + <lnA_bar, w_A>, and the central difference approximates
+it to O(h^2) (ln(1 + h w) - ln(1 - h w) = 2 h w + O(h^3)).
+
+Criteria:
+  * central differences: |fd - adj| <= 1e-6 |adj| per direction (the
+    survey's relative step and bound: the truncation error is O(h^2) times
+    third derivatives of the rates, ~1e-9 here, and the FP64 rounding of the
+    difference quotient is ~1e-16 |f| / h);
+  * oracle: |<vbar, J_oracle w> - adj| <= 1e-10 |adj| (dual-number tangent
+    products of the oracle's right-hand side and SDC step).
+The library is called through its C-ABI; the oracle's conserved state is
+uploaded, so both sides differentiate at the same point."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import adjoint as OA
+from synth import mechanism
+from synth.workloads import WORKLOADS, make_primitives, time_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1309_7327_amd import narrowsdc as N  # noqa: E402
+import gpu_util as G  # noqa: E402
+
+H = 1e-6
+NDIR = 200
+FD_TOL = 1e-6
+ORACLE_TOL = 1e-10
+WL = WORKLOADS["box64_adjoint"]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    m = mechanism.load(WL["mech"])
+    om = oracle.Mechanism(m)
+    ctx = N.Context(0)
+    ctx.set_mechanism(m)
+    U = oracle.prim_to_cons(om, make_primitives("box64_adjoint", m))
+    yield m, om, ctx, U
+    ctx.close()
+
+
+def direction(j, shape, nr):
+    rng = np.random.default_rng(5000 + j)
+    return rng.standard_normal(shape), rng.standard_normal(nr)
+
+
+def _perturbed(ctx, Ud, wd, lnA0, wA, sgn):
+    """Device state U (1 + sgn h w_U) and prefactors A (1 + sgn h w_A)."""
+    Up = torch.zeros_like(Ud)
+    N.interior(Up).copy_(N.interior(Ud) * (1.0 + sgn * H * wd))
+    ctx.set_log_prefactors(lnA0 + np.log1p(sgn * H * wA))
+    return Up
+
+
+def test_rhs_vjp_central_differences_200_directions(setup):
+    m, om, ctx, U = setup
+    lnA0 = np.log(np.asarray(m["A"], dtype=np.float64))
+    bx, Ud = G.upload(U, WL["dx"])
+    v = np.random.default_rng(5001).standard_normal(U.shape)
+    vd = G.dev(v)
+    Ub = torch.zeros(U.shape, dtype=torch.float64, device="cuda")
+    lA = torch.zeros(m["nr"], dtype=torch.float64, device="cuda")
+    ctx.rhs_vjp(bx, Ud, vd, Ub, lA)
+    ctx.check_status()
+    gA = G.host(lA)
+    Ui = G.dev(U)
+    F = torch.empty(U.shape, dtype=torch.float64, device="cuda")
+    worst, rels = 0.0, []
+    print("rhs_vjp 64^3: 200 central-difference directions", flush=True)
+    try:
+        for j in range(NDIR):
+            w, wA = direction(j, U.shape, m["nr"])
+            wd = G.dev(w)
+            dots = []
+            for sgn in (1.0, -1.0):
+                Up = _perturbed(ctx, Ud, wd, lnA0, wA, sgn)
+                ctx.rhs_eval(bx, Up, F, N.RHS_ALL)
+                dots.append(float(torch.sum(vd * F)))
+            ctx.check_status()
+            fd = (dots[0] - dots[1]) / (2 * H)
+            adj = float(torch.sum(Ub * Ui * wd)) + float(np.dot(gA, wA))
+            rel = abs(fd - adj) / abs(adj)
+            rels.append(rel)
+            worst = max(worst, rel)
+            if j < 5:
+                # the oracle's tangent product in the same direction
+                ctx.set_log_prefactors(lnA0)
+                _, jw = oracle.rhs_jvp(om, U, WL["dx"], U * w, wA)
+                ref = float(np.sum(v * jw))
+                ro = abs(ref - adj) / abs(ref)
+                print(f"  dir {j}: fd {fd:.12e} adjoint {adj:.12e} rel {rel:.1e}; oracle {ref:.15e} rel {ro:.1e}",
+                      flush=True)
+                assert ro <= ORACLE_TOL
+    finally:
+        ctx.set_log_prefactors(lnA0)
+    print(f"  central differences: max rel {worst:.2e}, median {np.median(rels):.2e}", flush=True)
+    assert worst <= FD_TOL
+
+
+def _sdc_vjp(ctx, m, bx, Ud, dt, nsteps, sch, ub):
+    nb = ctx.vjp_workspace_size(bx, sch, nsteps)
+    ws = torch.empty(nb // 8 + 1, dtype=torch.float64, device="cuda")
+    U0b = torch.empty(ub.shape, dtype=torch.float64, device="cuda")
+    lA = torch.zeros(m["nr"], dtype=torch.float64, device="cuda")
+    ctx.sdc_step_vjp(bx, Ud, dt, nsteps, sch, ub, U0b, lA, ws, nb)
+    ctx.check_status()
+    return U0b, G.host(lA)
+
+
+def test_sdc_step_vjp_central_differences_200_directions(setup):
+    """5 single-rate SDC steps (4 Gauss-Lobatto nodes, 6 sweeps)."""
+    m, om, ctx, U = setup
+    lnA0 = np.log(np.asarray(m["A"], dtype=np.float64))
+    dt = time_step("box64_adjoint")
+    nsteps = WL["steps"]
+    sch = N.scheme(4, 6, 0, 1)
+    bx, Ud = G.upload(U, WL["dx"])
+    ub = G.dev(np.random.default_rng(6001).standard_normal(U.shape))
+    g, gA = _sdc_vjp(ctx, m, bx, Ud, dt, nsteps, sch, ub)
+    ws, nb = N.workspace(ctx, [bx], sch)
+    Ui = G.dev(U)
+    worst, rels = 0.0, []
+    print("sdc_step_vjp 64^3, 5 steps: 200 central-difference directions", flush=True)
+    try:
+        for j in range(NDIR):
+            w, wA = direction(j, U.shape, m["nr"])
+            wd = G.dev(w)
+            dots = []
+            for sgn in (1.0, -1.0):
+                Up = _perturbed(ctx, Ud, wd, lnA0, wA, sgn)
+                ctx.sdc_step(bx, Up, dt, nsteps, sch, ws, nb)
+                dots.append(float(torch.sum(ub * N.interior(Up))))
+            ctx.check_status()
+            fd = (dots[0] - dots[1]) / (2 * H)
+            adj = float(torch.sum(g * Ui * wd)) + float(np.dot(gA, wA))
+            rel = abs(fd - adj) / abs(adj)
+            rels.append(rel)
+            worst = max(worst, rel)
+            if j < 3:
+                print(f"  dir {j}: fd {fd:.12e} adjoint {adj:.12e} rel {rel:.1e}", flush=True)
+    finally:
+        ctx.set_log_prefactors(lnA0)
+    print(f"  central differences: max rel {worst:.2e}, median {np.median(rels):.2e}", flush=True)
+    assert worst <= FD_TOL
+
+
+def test_sdc_step_vjp_against_oracle_tangent_box64(setup):
+    """One SDC step of the 64^3 workload: <ubar, dU_1> from the oracle's
+    tangent SDC run (eq. expsdc on the pair (U, dU), dual numbers) against
+    the library's adjoint, in direction 0."""
+    m, om, ctx, U = setup
+    dt = time_step("box64_adjoint")
+    sch = N.scheme(4, 6, 0, 1)
+    bx, Ud = G.upload(U, WL["dx"])
+    ubh = np.random.default_rng(6001).standard_normal(U.shape)
+    g, gA = _sdc_vjp(ctx, m, bx, Ud, dt, 1, sch, G.dev(ubh))
+    w, wA = direction(0, U.shape, m["nr"])
+    print("sdc_step_vjp 64^3, 1 step, oracle tangent", flush=True)
+    _, dU = OA.sdc_tangent(om, U, WL["dx"], dt, 4, 6, 1, U * w, wA)
+    ref = float(np.sum(ubh * dU))
+    adj = float(np.sum(G.host(g) * U * w) + np.dot(gA, wA))
+    rel = abs(ref - adj) / abs(ref)
+    print(f"  oracle {ref:.15e} adjoint {adj:.15e} rel {rel:.1e}", flush=True)
+    assert rel <= ORACLE_TOL

@@ -29,11 +29,16 @@ def setup():
     return m, oracle.Mechanism(m), ctx
 
 
-def _states(ctx, m, idx):
+def _states(ctx, m, idx, om=None):
+    """Device states of the boxes idx: the library's own conversion, or with
+    om the oracle's conserved state uploaded (for oracle comparisons)."""
     boxes, Us = [], []
     for b in idx:
         prim = fields.sines(SHAPES[b], WL["dx"], m["ns"], WL["seed"] + b)
-        bx, U = G.device_state(ctx, prim, WL["dx"])
+        if om is None:
+            bx, U = G.device_state(ctx, prim, WL["dx"])
+        else:
+            bx, U, _ = G.oracle_state(om, prim, WL["dx"])
         boxes.append(bx)
         Us.append(U)
     return boxes, Us
@@ -74,7 +79,7 @@ def test_batched_boxes_match_oracle(setup):
     # the two smallest boxes of the batch, advanced together with a large one
     order = np.argsort([np.prod(s) for s in SHAPES])
     idx = [int(order[0]), int(order[1]), int(order[-1])]
-    boxes, Us = _states(ctx, m, idx)
+    boxes, Us = _states(ctx, m, idx, om)
     sch = N.scheme(4, 6, 0, 1)
     _run_batched(ctx, boxes, Us, sch, 1, dt)
     for j in range(2):

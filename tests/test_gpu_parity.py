@@ -54,11 +54,10 @@ def test_prim_to_cons(kind, shape):
 def test_rhs_eval_parity(kind, shape, dx, parts):
     m, om, ctx = mech(kind)
     prim = fields.sines(shape, dx, m["ns"], 11)
-    bx, U = G.device_state(ctx, prim, dx)
+    bx, U, Uo = G.oracle_state(om, prim, dx)
     F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
     ctx.rhs_eval(bx, U, F, parts)
     ctx.check_status()
-    Uo = oracle.prim_to_cons(om, prim)
     fref, floor = G.ulp_floor(lambda V: oracle.rhs(om, V, dx, parts=parts), Uo)
     ok, rep = G.compare(G.host(F), fref, floor)
     print(kind, shape, parts, G.fmt(rep))
@@ -110,12 +109,11 @@ def _run_gpu_sdc(ctx, bx, U, dt, sch, nsteps):
 def test_sdc_step_parity(kind, shape, sch, nsteps):
     m, om, ctx = mech(kind)
     prim = fields.sines(shape, 1e-4, m["ns"], 13)
-    bx, U = G.device_state(ctx, prim, 1e-4)
-    U0g = G.interior(G.host(U)).copy()
+    bx, U, U0 = G.oracle_state(om, prim, 1e-4)
+    U0g = U0
     dt = time_step("box16_sdc")
     _run_gpu_sdc(ctx, bx, U, dt, sch, nsteps)
     Ug = G.interior(G.host(U))
-    U0 = oracle.prim_to_cons(om, prim)
     ref, floor, dfloor = G.ulp_floor_step(lambda V, pt: _sdc_oracle(om, V, 1e-4, dt, sch, nsteps, pt), U0)
     ok, rep = G.compare(Ug, ref, floor)
     okd, repd = G.compare(Ug - U0g, ref - U0, dfloor, state=ref)
@@ -134,16 +132,16 @@ def test_full_size_step_on_periodic_tiling(name):
     n = wl["shape"][0]
     small = make_primitives(name, m, shape_override=(16, 16, 16))
     reps = (n // 16,) * 3
-    big = fields.tile(small, reps)
-    bx, U = G.device_state(ctx, big, wl["dx"])
+    U0s = oracle.prim_to_cons(om, small)
+    reps_q = (1,) + reps
+    bx, U = G.upload(np.tile(U0s, reps_q), wl["dx"])
     dt = time_step(name)
     sch = dict(wl["scheme"])
-    U0g = G.interior(G.host(U))[:, :16, :16, :16].copy()
+    U0g = U0s
     _run_gpu_sdc(ctx, bx, U, dt, sch, 1)
     Ug = G.interior(G.host(U))
     del U
     torch.cuda.empty_cache()
-    U0s = oracle.prim_to_cons(om, small)
     ref, floor, dfloor = G.ulp_floor_step(lambda V, pt: _sdc_oracle(om, V, wl["dx"], dt, sch, 1, pt), U0s)
     reps_q = (1,) + reps
     ok, rep = G.compare(Ug, np.tile(ref, reps_q), floor)
@@ -159,13 +157,12 @@ def test_sampled_cells_of_full_size_rhs():
     wl = WORKLOADS[name]
     m, om, ctx = mech(wl["mech"])
     prim = make_primitives(name, m)
-    bx, U = G.device_state(ctx, prim, wl["dx"])
+    bx, U, Ui = G.oracle_state(om, prim, wl["dx"])
     shape = wl["shape"]
     F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
     ctx.rhs_eval(bx, U, F, N.RHS_ALL)
     ctx.check_status()
     Fh = G.host(F)
-    Ui = oracle.prim_to_cons(om, prim)
     rng = np.random.default_rng(3)
     cells = rng.integers(0, shape[0], size=(96, 3))
     cells[:8] = [[0, 0, 0], [127, 127, 127], [0, 127, 3], [64, 0, 127], [1, 2, 3], [126, 1, 0], [3, 3, 126], [127, 0, 0]]
@@ -189,11 +186,11 @@ def test_rhs_eval_other_stencil_parameters(params):
     ctx.set_mechanism(m)
     shape, dx = (10, 9, 12), 1e-4
     prim = fields.sines(shape, dx, m["ns"], 17)
-    bx, U = G.device_state(ctx, prim, dx)
+    bx, U, Uo = G.oracle_state(om, prim, dx)
     F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
     ctx.rhs_eval(bx, U, F, N.RHS_DIFF)
     ctx.check_status()
-    fref, floor = G.ulp_floor(lambda V: oracle.rhs(om, V, dx, parts=oracle.DIFF), oracle.prim_to_cons(om, prim))
+    fref, floor = G.ulp_floor(lambda V: oracle.rhs(om, V, dx, parts=oracle.DIFF), Uo)
     ok, rep = G.compare(G.host(F), fref, floor)
     print(params, G.fmt(rep))
     assert ok, G.fmt(rep)

@@ -36,11 +36,10 @@ def _ctx(kind, ref):
 def test_reference_species_rhs_parity(kind, shape, dx, ref, parts):
     m, om, ctx = _ctx(kind, ref)
     prim = fields.sines(shape, dx, m["ns"], 21)
-    bx, U = G.device_state(ctx, prim, dx)
+    bx, U, Uo = G.oracle_state(om, prim, dx)
     F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
     ctx.rhs_eval(bx, U, F, parts)
     ctx.check_status()
-    Uo = oracle.prim_to_cons(om, prim)
     fref, floor = G.ulp_floor(lambda V: oracle.rhs(om, V, dx, parts=parts), Uo)
     ok, rep = G.compare(G.host(F), fref, floor)
     print(kind, shape, ref, parts, G.fmt(rep))
@@ -54,8 +53,8 @@ def test_reference_species_sdc_step_parity(sch, nsteps):
     m, om, ctx = _ctx("mech9le", 8)
     shape = (6, 5, 7)
     prim = fields.sines(shape, 1e-4, m["ns"], 23)
-    bx, U = G.device_state(ctx, prim, 1e-4)
-    U0g = G.interior(G.host(U)).copy()
+    bx, U, U0 = G.oracle_state(om, prim, 1e-4)
+    U0g = U0
     dt = time_step("box16_sdc")
     s = N.scheme(sch["n_coarse"], sch["sweeps"], sch["n_fine"], sch.get("fine_repeat", 1))
     ws, nb = N.workspace(ctx, [bx], s)
@@ -71,8 +70,6 @@ def test_reference_species_sdc_step_parity(sch, nsteps):
         f2 = lambda W, t: oracle.rhs(om, W, 1e-4, parts=oracle.REACT)
         t1, t2, pieces = osdc.mr_nodes(sch["n_coarse"], sch["n_fine"], sch["fine_repeat"])
         return osdc.mrsdc_run(f1, f2, V, 0.0, dt, t1, t2, pieces, sch["sweeps"], nsteps, pt)
-
-    U0 = oracle.prim_to_cons(om, prim)
     ref, floor, dfloor = G.ulp_floor_step(step, U0)
     ok, rep = G.compare(Ug, ref, floor)
     okd, repd = G.compare(Ug - U0g, ref - U0, dfloor, state=ref)
@@ -89,13 +86,12 @@ def test_sampled_cells_of_full_size_reference_species_rhs():
     wl = WORKLOADS[name]
     m, om, ctx = _ctx(wl["mech"], wl["ref_species"])
     prim = make_primitives(name, m)
-    bx, U = G.device_state(ctx, prim, wl["dx"])
+    bx, U, Ui = G.oracle_state(om, prim, wl["dx"])
     shape = wl["shape"]
     F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
     ctx.rhs_eval(bx, U, F, N.RHS_ALL)
     ctx.check_status()
     Fh = G.host(F)
-    Ui = oracle.prim_to_cons(om, prim)
     rng = np.random.default_rng(5)
     cells = rng.integers(0, shape[0], size=(48, 3))
     cells[:4] = [[0, 0, 0], [127, 127, 127], [0, 127, 3], [64, 0, 127]]

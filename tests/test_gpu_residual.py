@@ -26,15 +26,15 @@ def _ctx(kind):
 
 
 @pytest.mark.parametrize("kind,shape,K,ratio,nsteps", [
-    ("mech9", (8, 8, 8), 14, 1.5, 2),        # stops once the residual reaches rounding level
+    ("mech9", (8, 8, 8), 14, 30.0, 3),       # each step stops after 3 sweeps (ratios 142/9.4, 91/15, 65/22)
     ("mech9le", (6, 5, 7), 10, 20.0, 1),     # stops after 3 sweeps, the residual still shrinking (ratios 122, 11)
 ])
 def test_residual_exit_parity(kind, shape, K, ratio, nsteps):
     m, om, ctx = _ctx(kind)
     ctx.set_residual_exit(ratio)
     prim = fields.sines(shape, 1e-4, m["ns"], 13)
-    bx, U = G.device_state(ctx, prim, 1e-4)
-    U0g = G.interior(G.host(U)).copy()
+    bx, U, U0 = G.oracle_state(om, prim, 1e-4)
+    U0g = U0
     dt = time_step("box16_sdc")
     s = N.scheme(4, K, 0, 1)
     ws, nb = N.workspace(ctx, [bx], s)
@@ -42,7 +42,6 @@ def test_residual_exit_parity(kind, shape, K, ratio, nsteps):
     ctx.check_status()
     norms, sweeps = ctx.residual_history()
     Ug = G.interior(G.host(U))
-    U0 = oracle.prim_to_cons(om, prim)
     hist = []
     f = lambda V, t: oracle.rhs(om, V, 1e-4)
     ref = osdc.sdc_run(f, U0, 0.0, dt, osdc.gauss_lobatto(4), K, nsteps, residual_ratio=ratio, history=hist)
@@ -50,14 +49,25 @@ def test_residual_exit_parity(kind, shape, K, ratio, nsteps):
     osw = [h[1] for h in hist if h[0] == "sweeps"]
     print("sweeps", sweeps, osw, "residuals", norms, rs)
     assert sweeps < nsteps * K
-    # the decisions agree where the residual is above rounding level; at
-    # rounding level a step may take one sweep more or less
-    assert abs(sweeps - sum(osw)) <= nsteps
+    # every exit decision of these cases is far from the threshold (at least
+    # 5% in the ratio) and taken on residuals far above rounding level
+    # (>= 1e-10 of max|U_0|), where the two sides' residuals agree to ~1e-12
+    # relative: the sweep counts must agree exactly
+    prev = None
+    for h in hist:
+        if h[0] == "sweeps":
+            prev = None
+            continue
+        assert h[2] > 1e-10
+        if prev is not None:
+            assert abs(np.log(prev / h[2]) - np.log(ratio)) > np.log(1.05), (prev, h[2])
+        prev = h[2]
+    assert sweeps == sum(osw)
     # the residual is a difference of states of order one (relative to
     # max|U_0|) formed in another rounding order: it agrees to rounding level
     # in absolute terms, 1e-14 (about 50 ulp), and to 1e-6 where it is large
-    n = min(len(norms), len(rs))
-    np.testing.assert_allclose(norms[:n], rs[:n], rtol=1e-6, atol=1e-14)
+    assert len(norms) == len(rs)
+    np.testing.assert_allclose(norms, rs, rtol=1e-6, atol=1e-14)
     _, floor, dfloor = G.ulp_floor_step(
         lambda V, pt: osdc.sdc_run(f, V, 0.0, dt, osdc.gauss_lobatto(4), K, nsteps, pt, residual_ratio=ratio), U0)
     ok, rep = G.compare(Ug, ref, floor)
