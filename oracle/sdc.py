@@ -193,3 +193,54 @@ def mrsdc_run(f1, f2, U0, t0, dt, t1, t2, pieces, K, nsteps, perturb=None):
             F1k, F2k = F1n, F2n
         U0, F1_0, F2_0 = U, F1k[M1], F2k[M2]
     return U0
+
+
+def mrsdc2_run(f1, solve1, f2, U0, t0, dt, t1, t2, pieces, K, nsteps, perturb=None):
+    """Multirate SDC, mode 2 (eq. mrupdate2): the stiff component f1 (the
+    chemistry) on the coarse nodes t1, treated implicitly; f2 (advection-
+    diffusion) on the fine nodes t2 with forward-Euler corrections.
+
+    In coarse interval p the fine updates of eq. (mrupdate2) hold
+    f1(U^{k+1}_{p+1}) fixed.  It is obtained first, by an implicit solve over
+    the interval: U* = U^{k+1}_p + dt_p (f1(U*) - F1^k_{p+1})
+    + dt sum_{q in p} (S21 F1^k + S22 F2^k)_q, i.e. one backward-Euler step of
+    f1 (first-order BDF) with the interval's explicit update as forcing and
+    the fine correction terms of f2 lagged; solve1(rhs, h) returns U* with
+    U* - h f1(U*) = rhs.  X = f1(U*) is the new F1 at node p+1, and the fine
+    sub-steps of the interval use it.  At the SDC fixed point U* is the
+    interval's end state, so the sweeps converge to the multirate collocation
+    solution, as in mode 1.  f1 of the end state starts the next step, f2 of
+    it is the last sweep's.  perturb as in sdc_run."""
+    perturb = perturb or (lambda U: U)
+    M1, M2 = len(t1) - 1, len(t2) - 1
+    r = M2 // M1
+    assert r * M1 == M2
+    S21, S22 = mr_matrices(t1, t2, pieces)
+    dtq = np.diff(t2) * dt
+    dtp = np.diff(t1) * dt
+    U0 = np.array(U0, copy=True)
+    F1_0 = f1(U0, t0)
+    F2_0 = f2(U0, t0)
+    for n in range(nsteps):
+        tn = t0 + n * dt
+        F1k = [F1_0] * (M1 + 1)
+        F2k = [F2_0] * (M2 + 1)
+        for k in range(K):
+            F1n = [F1_0] + [None] * M1
+            F2n = [F2_0] + [None] * M2
+            U = U0
+            for p in range(M1):
+                qs = range(p * r, (p + 1) * r)
+                Sq = {q: dt * (sum(S22[q, j] * F2k[j] for j in range(M2 + 1)) +
+                               sum(S21[q, j] * F1k[j] for j in range(M1 + 1))) for q in qs}
+                rhs = U - dtp[p] * F1k[p + 1] + sum(Sq[q] for q in qs)
+                X = f1(solve1(rhs, dtp[p]), tn + t1[p + 1] * dt)
+                F1n[p + 1] = X
+                for q in qs:
+                    if q > 0:
+                        F2n[q] = f2(U, tn + t2[q] * dt)
+                    U = perturb(U + dtq[q] * (X - F1k[p + 1]) + dtq[q] * (F2n[q] - F2k[q]) + Sq[q])
+            F2n[M2] = f2(U, tn + dt)
+            F1k, F2k = F1n, F2n
+        U0, F1_0, F2_0 = U, f1(U, tn + dt), F2k[M2]
+    return U0
