@@ -119,6 +119,30 @@ int prim_to_cons(sdc_context *ctx, const box_desc *box, const double *p, const d
 int rhs_eval(sdc_context *ctx, const box_desc *box, double *U, double *dUdt, unsigned parts,
              void *stream);
 
+/* Size of the library's static scratch array (64 MiB), the device memory of
+ * rhs_eval_static.  Each GPU the library runs on holds one copy of it until
+ * the process ends. */
+#define NSDC_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* rhs_eval for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (bit for bit) as rhs_eval, but the work
+ * list, primitives and velocity gradients live in the static scratch array
+ * instead of context scratch, so the call makes no hipMalloc, hipFree or
+ * other device or pinned allocation (the context's creation set up the
+ * array's address and a pinned staging buffer for the work list, which the
+ * call copies to the device on `stream`).
+ * Limit: the box's scratch (work list, (8 + 3 ns + 9) doubles per ghosted
+ * cell) must fit NSDC_STATIC_SCRATCH_BYTES, e.g. a 48^3 box with 9 species
+ * or a 32^3 box with 21; larger boxes return SDC_EINVAL (use rhs_eval).
+ * Every call on one GPU shares that GPU's array and it keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other contexts,
+ * other threads) race and must be ordered by the caller.  The profiler
+ * (sdc_profile_enable) does not time these launches.  SDC_EHIP if the array's
+ * address could not be obtained at context creation. */
+int rhs_eval_static(sdc_context *ctx, const box_desc *box, double *U, double *dUdt, unsigned parts,
+                    void *stream);
+
 /* Bytes of device workspace sdc_step / sdc_step_batched need. */
 int sdc_workspace_size(const sdc_context *ctx, int nbox, const box_desc *boxes,
                        const sdc_scheme *scheme, size_t *bytes);

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -260,7 +261,54 @@ struct sdc_context {
   std::vector<double> resid_hist;       // residuals measured by the last sdc_step call
   int last_sweeps = 0;                  // sweeps performed by the last sdc_step call
   std::map<std::string, hipGraphExec_t> graphs;
+  // rhs_eval_static: this device's copy of the static scratch array, and a
+  // pinned staging buffer (allocated here, at creation) through which the
+  // work list reaches it; stage_done marks the last upload's completion
+  double *static_scratch = nullptr;
+  void *stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
 };
+
+// ------------------------------------------------------------ static scratch
+// Device memory of rhs_eval_static (its work list, primitives and velocity
+// gradients): a file-scope array instead of hipMalloc.  Every GPU the library
+// runs on holds its own copy, at its own address, until the process ends.
+// Host code uses that address (from hipGetSymbolAddress, kept per device),
+// never the array's name, which on the host is only a stand-in.
+static __device__ __align__(256) double scratch[NSDC_STATIC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+std::mutex g_static_mu;
+std::map<int, double *> g_static_ptr;
+
+// This GPU's copy of the static scratch array; `device` must be current.
+hipError_t static_scratch_address(int device, double **out) {
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  auto it = g_static_ptr.find(device);
+  if (it != g_static_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    *out = nullptr;
+    return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  }
+  g_static_ptr[device] = static_cast<double *>(ptr);
+  *out = static_cast<double *>(ptr);
+  return hipSuccess;
+}
+
+// pinned staging for the work list of rhs_eval_static: 1 MiB holds 65536
+// work items (a 48^3 box with the default tiles needs about 3000); longer
+// lists are rejected
+constexpr size_t STAGE_BYTES = size_t(1) << 20;
+
+}  // namespace
 
 namespace {
 
@@ -307,11 +355,12 @@ std::string box_signature(int nbox, const box_desc *b) {
   return k;
 }
 
-int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Plan **out) {
-  TileShape tI{}, tS{};
+// Tile shapes and persistent-grid size of a box set: forced by sdc_set_tiles,
+// autotuned, or the defaults.
+void plan_shape(const sdc_context *c, int nbox, const box_desc *bx, TileShape &tI, TileShape &tS, int &cap) {
   // batches run as persistent launches: a few workgroups per compute unit
   // walk the (box, tile) list
-  int cap = nbox > 1 ? 4 * std::max(c->n_cu, 1) : 0;
+  cap = nbox > 1 ? 4 * std::max(c->n_cu, 1) : 0;
   auto tu = c->forceI.tx ? c->tuned.end() : c->tuned.find(box_signature(nbox, bx));
   if (c->forceI.tx) {
     tI = c->forceI;
@@ -331,28 +380,21 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
     tI = default_tile(mx, my, mz);
     tS = default_tile(nbox > 1 ? 16 : mx + 8, my + 8, mz + 8);
   }
-  std::string key = plan_key(nbox, bx, U, tI, tS) + "|cap" + std::to_string(cap) + "|gc" +
-                    std::to_string(c->grid_cap);
-  auto it = c->plans.find(key);
-  if (it != c->plans.end()) {
-    *out = it->second.get();
-    return SDC_OK;
-  }
-  if (c->plans.size() > 512) {
-    drop_graphs(c);
-    c->plans.clear();
-  }
-  auto p = std::make_unique<Plan>();
-  p->nbox = nbox;
-  p->boxes.assign(bx, bx + nbox);
-  p->tsI = tI;
-  p->tsS = tS;
+}
+
+// Host side of a work plan for p->boxes with p's tile shapes: the per-box
+// descriptors and the work lists (interior, stored, ghost, interior with y
+// fastest, z-pass tiles), each in XCD order, back to back.
+void plan_layout(const sdc_context *c, Plan *p, std::vector<BoxDev> &hb, std::vector<Item> &all) {
+  const int nbox = p->nbox;
+  const box_desc *bx = p->boxes.data();
+  const TileShape tI = p->tsI, tS = p->tsS;
   // the z pass takes the interior tile with its y and z extents exchanged:
   // its waves then share the z-lines' planes
   const TileShape tZ{tI.tx, tI.tz, tI.ty};
   p->tsZ = tZ;
-  p->cap = cap;
-  std::vector<BoxDev> hb(nbox);
+  p->totS = p->totI = 0;
+  hb.assign(nbox, BoxDev{});
   std::vector<Item> iI, iS, iG, iY, iZ;
   for (int b = 0; b < nbox; ++b) {
     BoxDev &d = hb[b];
@@ -388,12 +430,38 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
   p->nS = (int)iS.size();
   p->nG = (int)iG.size();
   p->nZ = (int)iZ.size();
-  const long long capE = c->grid_cap > 0 ? c->grid_cap : (cap > 0 ? cap : (1LL << 30));
-  std::vector<Item> all;
+  const long long capE = c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : (1LL << 30));
+  all.clear();
   for (const std::vector<Item> *v : {&iI, &iS, &iG, &iY, &iZ}) {
     const std::vector<Item> o = xcd_order(*v, std::min<long long>((long long)v->size(), capE));
     all.insert(all.end(), o.begin(), o.end());
   }
+}
+
+int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Plan **out) {
+  TileShape tI{}, tS{};
+  int cap = 0;
+  plan_shape(c, nbox, bx, tI, tS, cap);
+  std::string key = plan_key(nbox, bx, U, tI, tS) + "|cap" + std::to_string(cap) + "|gc" +
+                    std::to_string(c->grid_cap);
+  auto it = c->plans.find(key);
+  if (it != c->plans.end()) {
+    *out = it->second.get();
+    return SDC_OK;
+  }
+  if (c->plans.size() > 512) {
+    drop_graphs(c);
+    c->plans.clear();
+  }
+  auto p = std::make_unique<Plan>();
+  p->nbox = nbox;
+  p->boxes.assign(bx, bx + nbox);
+  p->tsI = tI;
+  p->tsS = tS;
+  p->cap = cap;
+  std::vector<BoxDev> hb;
+  std::vector<Item> all;
+  plan_layout(c, p.get(), hb, all);
   HIPCHECK(c, hipMalloc(&p->d_boxes, sizeof(BoxDev) * nbox));
   HIPCHECK(c, hipMemcpy(p->d_boxes, hb.data(), sizeof(BoxDev) * nbox, hipMemcpyHostToDevice));
   HIPCHECK(c, hipMalloc(&p->d_items, sizeof(Item) * all.size()));
@@ -408,13 +476,15 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
   return SDC_OK;
 }
 
-LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
+// Launch context of a plan whose box descriptors and work lists are at
+// d_boxes and d_items on the device.
+LaunchCtx make_lc_at(sdc_context *c, const Plan *p, BoxDev *d_boxes, Item *d_items, hipStream_t s) {
   LaunchCtx l;
   l.stream = s;
-  l.boxes = p->d_boxes;
-  l.itemsI = p->d_items;
-  l.itemsS = p->d_items + p->nI;
-  l.itemsG = p->d_items + p->nI + p->nS;
+  l.boxes = d_boxes;
+  l.itemsI = d_items;
+  l.itemsS = d_items + p->nI;
+  l.itemsG = d_items + p->nI + p->nS;
   l.itemsD[0] = l.itemsI;
   l.itemsD[1] = l.itemsG + p->nG;
   l.itemsD[2] = l.itemsD[1] + p->nI;
@@ -436,6 +506,10 @@ LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
   l.prof = c->prof.get();
   l.smc_stencil = c->smc_stencil;
   return l;
+}
+
+LaunchCtx make_lc(sdc_context *c, Plan *p, hipStream_t s) {
+  return make_lc_at(c, p, p->d_boxes, p->d_items, s);
 }
 
 // One right-hand-side evaluation into F (interior) from U (ghosted).  warm:
@@ -755,6 +829,16 @@ int sdc_context_create(sdc_context **out, int device) {
     delete c;
     return SDC_EHIP;
   }
+  // rhs_eval_static's set-up (it allocates nothing itself): this device's
+  // static scratch address, the staging buffer and its event.  Failures
+  // leave that entry point unavailable (SDC_EHIP) and nothing else.
+  if (static_scratch_address(device, &c->static_scratch) != hipSuccess) c->static_scratch = nullptr;
+  if (hipHostMalloc(&c->stage, STAGE_BYTES, hipHostMallocDefault) == hipSuccess)
+    c->stage_bytes = STAGE_BYTES;
+  else
+    c->stage = nullptr;
+  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) c->stage_done = nullptr;
+  (void)hipGetLastError();
   *out = c;
   return SDC_OK;
 }
@@ -772,6 +856,8 @@ int sdc_context_destroy(sdc_context *c) {
   c->fine_tabs.clear();
   c->d_fine = nullptr;
   if (c->d_resid) (void)hipFree(c->d_resid);
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  if (c->stage) (void)hipHostFree(c->stage);
   delete c;
   return SDC_OK;
 }
@@ -920,6 +1006,53 @@ int rhs_eval(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsig
   double *G = P + ((((size_t)pl->totS * (8 + 3 * ns)) + 31) & ~size_t(31));
   const LaunchCtx l = make_lc(c, pl, (hipStream_t)stream);
   eval_rhs_g(c->ops, l, FRef{U, nullptr}, P, G, FRef{dUdt, nullptr}, parts);
+  HIPCHECK(c, hipGetLastError());
+  return SDC_OK;
+}
+
+int rhs_eval_static(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsigned parts,
+                    void *stream) {
+  if (!c) return SDC_EINVAL;
+  if (!c->has_mech) return fail(c, SDC_ENOMECH, "no mechanism set");
+  int rc = check_box(c, box);
+  if (rc) return rc;
+  if (!U || !dUdt) return fail(c, SDC_EINVAL, "null field pointer");
+  if (parts == 0 || (parts & ~7u)) return fail(c, SDC_EINVAL, "bad parts mask");
+  HIPCHECK(c, hipSetDevice(c->device));
+  if (!c->static_scratch || !c->stage || !c->stage_done)
+    return fail(c, SDC_EHIP, "static scratch unavailable on this device");
+  // the work plan's host side only; its device lists go to the scratch
+  Plan p;
+  p.nbox = 1;
+  p.boxes.assign(box, box + 1);
+  plan_shape(c, 1, box, p.tsI, p.tsS, p.cap);
+  std::vector<BoxDev> hb;
+  std::vector<Item> items;
+  plan_layout(c, &p, hb, items);
+  const int ns = c->ops->ns;
+  auto up256 = [](size_t n) { return (n + 255) & ~size_t(255); };
+  const size_t off_items = up256(sizeof(BoxDev));
+  const size_t off_P = up256(off_items + sizeof(Item) * items.size());
+  const size_t off_G = up256(off_P + sizeof(double) * (size_t)p.totS * (8 + 3 * ns));
+  const size_t need = off_G + sizeof(double) * ((size_t)p.totS * 9 + 64);
+  if (need > NSDC_STATIC_SCRATCH_BYTES)
+    return fail(c, SDC_EINVAL, "box needs " + std::to_string(need) + " bytes of static scratch, more than its " +
+                                   std::to_string((size_t)NSDC_STATIC_SCRATCH_BYTES) + " (use rhs_eval)");
+  if (off_P > c->stage_bytes) return fail(c, SDC_EINVAL, "work list longer than the staging buffer");
+  hipStream_t st = (hipStream_t)stream;
+  // the previous call's upload must have left the staging buffer
+  if (c->stage_pending) HIPCHECK(c, hipEventSynchronize(c->stage_done));
+  char *stage = static_cast<char *>(c->stage);
+  std::memcpy(stage, hb.data(), sizeof(BoxDev));
+  std::memcpy(stage + off_items, items.data(), sizeof(Item) * items.size());
+  char *base = reinterpret_cast<char *>(c->static_scratch);
+  HIPCHECK(c, hipMemcpyAsync(base, stage, off_P, hipMemcpyHostToDevice, st));
+  HIPCHECK(c, hipEventRecord(c->stage_done, st));
+  c->stage_pending = true;
+  LaunchCtx l = make_lc_at(c, &p, reinterpret_cast<BoxDev *>(base), reinterpret_cast<Item *>(base + off_items), st);
+  l.prof = nullptr;   // the profiler's events are created on demand
+  eval_rhs_g(c->ops, l, FRef{U, nullptr}, reinterpret_cast<double *>(base + off_P),
+             reinterpret_cast<double *>(base + off_G), FRef{dUdt, nullptr}, parts);
   HIPCHECK(c, hipGetLastError());
   return SDC_OK;
 }

@@ -51,6 +51,7 @@ _SIGS = {
     "set_mechanism": [_vp, ctypes.POINTER(MechanismDesc)],
     "prim_to_cons": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, _vp, _vp, _vp, _vp],
     "rhs_eval": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, ctypes.c_uint, _vp],
+    "rhs_eval_static": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, ctypes.c_uint, _vp],
     "sdc_workspace_size": [_vp, _ip, ctypes.POINTER(BoxDesc), ctypes.POINTER(Scheme),
                            ctypes.POINTER(ctypes.c_size_t)],
     "sdc_step": [_vp, ctypes.POINTER(BoxDesc), _vp, _d, _ip, ctypes.POINTER(Scheme), _vp,
@@ -168,6 +169,12 @@ class Context:
 
     def rhs_eval(self, bx, U, dUdt, parts=RHS_ALL, stream=None):
         self._check(_lib.rhs_eval(self.h, ctypes.byref(bx), _ptr(U), _ptr(dUdt), parts, _stream(stream)))
+
+    def rhs_eval_static(self, bx, U, dUdt, parts=RHS_ALL, stream=None):
+        """rhs_eval with the library's static scratch array (no device
+        allocation in the call; see the header for the size limit)."""
+        self._check(_lib.rhs_eval_static(self.h, ctypes.byref(bx), _ptr(U), _ptr(dUdt), parts,
+                                         _stream(stream)))
 
     def workspace_size(self, boxes, sch):
         arr = (BoxDesc * len(boxes))(*boxes)
