@@ -66,10 +66,21 @@ def work_model(ns, nr, n_coarse, n_fine_per_interval, fused=False):
     # in evaluations without the chemistry (the multirate coarse component)
     # the x pass stores dU/dt without reading it first
     dir_x_bytes = dir_bytes - (8 * nu if r else 0)
+    # multirate mode 2, implicit chemistry of one coarse interval per cell:
+    # the interval's forcing (read U, f1 at the n1 coarse nodes, f2 at the
+    # r + 1 fine nodes of the interval; write the new f1), then Newton's
+    # method: per iteration the rates and their Jacobian (the chemistry, 16
+    # sparse updates per reaction, the dense temperature column) and an LU
+    # solve; counted as 3 iterations and the final rate evaluation
+    nr_ = nr
+    jac = chem_flops + newton + 32 * nr_ + 3 * ns * ns + (2 * ns ** 3) // 3 + 2 * ns * ns
+    imp_flops = (n_coarse + r + 1) * nu * 2 + 4 * jac
+    imp_bytes = 8 * (nu + n_coarse * ns + (r + 1) * nu + ns)
     return {
         "dir_x": (dir_flops, dir_x_bytes), "dir_y": (dir_flops, dir_bytes), "dir_z": (dir_flops, dir_bytes),
         "mr_fine": (step_flops, step_bytes), "mr_src": (src_flops, src_bytes),
         "prims": (newton + 40 * ns, 8 * (nu + np_)),
+        "mr2_imp": (imp_flops, imp_bytes),
     }
 
 
@@ -96,8 +107,11 @@ def cpu_baseline(workload, mech, n_cells_full):
     from synth.workloads import WORKLOADS, make_primitives, time_step
     wl = WORKLOADS[workload]
     om = oracle.Mechanism(mech, ref_species=wl.get("ref_species", -1), wide=wl.get("wide", False))
-    # about 10-30 s of host work: a 64^3 box with 9 species, 48^3 with 21
-    edge = 64 if mech["ns"] <= 9 else 48
+    # about 10-30 s of host work: a 64^3 box with 9 species, 48^3 with 21,
+    # 24^3 for the implicit-chemistry scheme (its Newton solves take the
+    # oracle's tangent products)
+    sch = wl["scheme"]
+    edge = 24 if sch.get("mode", 1) == 2 else (64 if mech["ns"] <= 9 else 48)
     prim = make_primitives(workload, mech, shape_override=(edge,) * 3)
     U0 = oracle.prim_to_cons(om, prim)
     dt = time_step(workload)
@@ -109,6 +123,13 @@ def cpu_baseline(workload, mech, n_cells_full):
         f = lambda U, t: oracle.rhs(om, U, dx, nthreads=threads)
         osdc.sdc_run(f, U0, 0.0, dt, osdc.gauss_lobatto(sch["n_coarse"]), sch["sweeps"], 1,
                      residual_ratio=wl.get("residual_ratio", 0.0))
+    elif sch.get("mode", 1) == 2:
+        from oracle import implicit as OI
+        f1 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.REACT, nthreads=threads)
+        f2 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.AD, nthreads=threads)
+        solve1 = lambda rhs, h: OI.implicit_reaction(om, rhs, h, dx, nthreads=threads)
+        t1, t2, pieces = osdc.mr_nodes(sch["n_coarse"], sch["n_fine"], sch["fine_repeat"])
+        osdc.mrsdc2_run(f1, solve1, f2, U0, 0.0, dt, t1, t2, pieces, sch["sweeps"], 1)
     else:
         f1 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.AD, nthreads=threads)
         f2 = lambda U, t: oracle.rhs(om, U, dx, parts=oracle.REACT, nthreads=threads)
@@ -378,8 +399,10 @@ def run_box(args, workload, steps, warmup, with_baseline):
         sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], 0, 1)
         r = 0
     else:
-        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], sch_d["n_fine"], sch_d["fine_repeat"])
+        sch = N.scheme(sch_d["n_coarse"], sch_d["sweeps"], sch_d["n_fine"], sch_d["fine_repeat"],
+                       mode=sch_d.get("mode", 1))
         r = (sch_d["n_fine"] - 1) * sch_d["fine_repeat"]
+    mode2 = sch_d.get("mode", 1) == 2
 
     ctx = N.Context(0)
     ctx.set_mechanism(mech)
@@ -430,9 +453,13 @@ def run_box(args, workload, steps, warmup, with_baseline):
     # with the residual early exit the sweeps taken replace K per step
     n_ad = (sweeps_done if wl.get("residual_ratio") else steps * sch_d["sweeps"]) * M1
     n_r = n_ad * r if r else n_ad
+    if mode2:
+        # mode 2: advection-diffusion on the fine nodes, one implicit
+        # chemistry solve per coarse interval
+        n_ad, n_r = n_ad * r, n_ad
     # the one-kernel fine sub-steps run for four coarse nodes, four fine
     # sub-steps per interval and at most nine species
-    fused = ns <= 9 and sch_d["n_coarse"] == 4 and r == 4
+    fused = ns <= 9 and sch_d["n_coarse"] == 4 and r == 4 and not mode2
     model = work_model(ns, mech["nr"], sch_d["n_coarse"], r, fused)
     dominant = max(kern, key=lambda k: kern[k][0])
     dur_ms = kern[dominant][0] / kern[dominant][1]
@@ -467,7 +494,7 @@ def run_box(args, workload, steps, warmup, with_baseline):
                    ("reference species %d" % wl["ref_species"]) if wl.get("ref_species", -1) >= 0
                    else "correction velocity"},
         "mcell_ad_evals_per_s": ncell * n_ad / el / 1e6,
-        "mcell_r_evals_per_s": ncell * n_r / el / 1e6,
+        ("mcell_implicit_chem_solves_per_s" if mode2 else "mcell_r_evals_per_s"): ncell * n_r / el / 1e6,
         "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},
         "roofline": roof,
         "stencil_roofline": stencil,

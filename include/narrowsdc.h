@@ -84,15 +84,24 @@ typedef struct {
 } mechanism_desc;
 
 /* Time scheme.  n_fine == 0: single-rate SDC (eq. expsdc) on n_coarse
- * Gauss-Lobatto nodes with the full right-hand side.  n_fine >= 2: MRSDC
- * mode 1 (eq. mrupdate): advection-diffusion on the n_coarse Gauss-Lobatto
- * nodes, chemistry on n_fine Gauss-Lobatto nodes repeated fine_repeat times
- * inside every coarse interval (fine_repeat = 1: type (b); > 1: type (c)). */
+ * Gauss-Lobatto nodes with the full right-hand side.  n_fine >= 2: multirate
+ * SDC with n_coarse Gauss-Lobatto coarse nodes and n_fine Gauss-Lobatto nodes
+ * repeated fine_repeat times inside every coarse interval (fine_repeat = 1:
+ * type (b); > 1: type (c)), in one of the two modes of Section 3.2:
+ *   mode 1 (or 0): eq. (mrupdate), advection-diffusion on the coarse nodes,
+ *     chemistry on the fine nodes, both explicit;
+ *   mode 2: eq. (mrupdate2), the chemistry on the coarse nodes, implicit (in
+ *     each coarse interval a backward-Euler solve of the chemistry, by
+ *     Newton's method cell by cell, with the interval's explicit update as
+ *     forcing gives f1 at the interval's right node), advection-diffusion on
+ *     the fine nodes, explicit.  For stiff chemistry; a Newton solve that does
+ *     not converge sets the device error word (SDC_ETEMP from last_status). */
 typedef struct {
   int n_coarse;     /* 2..8 */
   int sweeps;       /* K >= 1 */
   int n_fine;       /* 0 or 2..9 */
   int fine_repeat;  /* >= 1 */
+  int mode;         /* multirate mode: 0 or 1 (mode 1), 2 (mode 2) */
 } sdc_scheme;
 
 /* Create a context on HIP device `device`.  Owns the device copy of the

@@ -220,7 +220,7 @@ static const char *KERNEL_NAMES[K_NKERNELS] = {
     "prim_to_cons", "ghost",     "prims",     "vgrad",     "dir_x",     "dir_y",
     "dir_z",        "chem",      "sdc_node",  "mr_fine",   "mr_src",    "dir_adj_x",
     "dir_adj_y",    "dir_adj_z", "chem_adj",  "vgrad_adj", "prims_adj", "fold",
-    "adj_linalg",   "sdc_resid"};
+    "adj_linalg",   "sdc_resid", "mr2_imp"};
 
 struct sdc_context {
   int device = 0;
@@ -539,6 +539,12 @@ int check_scheme(sdc_context *c, const sdc_scheme *s) {
     if ((s->n_fine - 1) * s->fine_repeat > NSDC_MAXFINE - 1)
       return fail(c, SDC_EINVAL, "too many fine sub-steps per coarse interval");
   }
+  if (s->mode < 0 || s->mode > 2) return fail(c, SDC_EINVAL, "mode must be 0, 1 or 2");
+  if (s->mode == 2) {
+    if (s->n_fine == 0) return fail(c, SDC_EINVAL, "multirate mode 2 needs fine nodes (n_fine >= 2)");
+    if ((s->n_fine - 1) * s->fine_repeat + 1 > NSDC_MAXFINE)
+      return fail(c, SDC_EINVAL, "too many fine nodes per coarse interval");
+  }
   return SDC_OK;
 }
 
@@ -552,6 +558,27 @@ WsLayout ws_layout(const Plan *p, int ns, const sdc_scheme *s) {
   WsLayout w{};
   const int nU = 5 + ns, nP = 8 + 3 * ns;
   const int M1 = s->n_coarse - 1;
+  if (s->n_fine != 0 && s->mode == 2) {
+    // mode 2: F1 = chemistry at the coarse nodes (ns per cell), F2 =
+    // advection-diffusion at the fine nodes (nU), two state buffers, and the
+    // implicit solve's lane slots in A
+    const int M2 = M1 * (s->n_fine - 1) * s->fine_repeat;
+    w.nUb = 2;
+    w.nF1 = 1 + 2 * M1;
+    w.nF2 = 1 + 2 * M2;
+    // (interior tiles have at most 256 cells)
+    const size_t lanes = (size_t)NSDC_MR2_MAXWG * 256;
+    size_t off = 0;
+    auto take = [&](size_t n) { size_t o = off; off += (n + 31) & ~size_t(31); return o; };
+    w.P = take((size_t)p->totS * nP);
+    w.G = take((size_t)p->totS * 9);
+    w.Ub = take((size_t)p->totS * nU * w.nUb);
+    w.F1 = take((size_t)p->totI * ns * w.nF1);
+    w.F2 = take((size_t)p->totI * nU * w.nF2);
+    w.A = take(lanes * NSDC_MR2_SLOT(ns));
+    w.total = off;
+    return w;
+  }
   const bool mr = s->n_fine != 0;
   const int M2 = mr ? M1 * (s->n_fine - 1) * s->fine_repeat : 0;
   w.nUb = mr ? 1 : 2;
@@ -622,6 +649,137 @@ int fine_tables(sdc_context *c, const sdc_scheme *s) {
   return SDC_OK;
 }
 
+// ------------------------------------------------ multirate SDC, mode 2
+// Eq. (mrupdate2): chemistry f1 on the coarse nodes, implicit; advection-
+// diffusion f2 on the fine nodes, explicit.  In every coarse interval p the
+// implicit kernel first solves for f1 at node p+1 (the interval's explicit
+// update as forcing, the f2 corrections of the interval lagged), then the
+// fine sub-steps evaluate f2 at their left node and update the state.  f1 of
+// the step's end state starts the next step; f2 of it is the last sweep's.
+int run_mrsdc2(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sdc_scheme *s, double *W,
+               const WsLayout &L, const LaunchCtx &l) {
+  const Ops *o = c->ops;
+  const int ns = o->ns, nU = 5 + ns;
+  const int M1 = s->n_coarse - 1, K = s->sweeps;
+  const int r = (s->n_fine - 1) * s->fine_repeat, M2 = M1 * r;
+  // fine nodes of the step and the multirate integration matrices (units of
+  // the step): S21 from the coarse interpolant, S22 from the fine piece
+  std::vector<long double> t1 = gauss_lobatto(s->n_coarse), g = gauss_lobatto(s->n_fine);
+  std::vector<long double> t2(M2 + 1);
+  for (int pi = 0; pi < M1; ++pi)
+    for (int rep = 0; rep < s->fine_repeat; ++rep) {
+      const long double lo = t1[pi] + (t1[pi + 1] - t1[pi]) * rep / s->fine_repeat;
+      const long double hi = t1[pi] + (t1[pi + 1] - t1[pi]) * (rep + 1) / s->fine_repeat;
+      for (int j = 0; j < s->n_fine; ++j) t2[pi * r + rep * (s->n_fine - 1) + j] = lo + (hi - lo) * g[j];
+    }
+  t2[M2] = 1.0L;
+  std::vector<std::vector<double>> S21(M2, std::vector<double>(M1 + 1)), S22(M2, std::vector<double>(M2 + 1, 0.0));
+  std::vector<int> plo(M2);
+  for (int q = 0; q < M2; ++q) {
+    for (int j = 0; j <= M1; ++j) S21[q][j] = (double)lagrange_integral(t1, j, t2[q], t2[q + 1]);
+    const int lo = (q / (s->n_fine - 1)) * (s->n_fine - 1);
+    plo[q] = lo;
+    std::vector<long double> loc(t2.begin() + lo, t2.begin() + lo + s->n_fine);
+    for (int j = 0; j < s->n_fine; ++j) S22[q][lo + j] = (double)lagrange_integral(loc, j, t2[q], t2[q + 1]);
+  }
+  double *P = W + L.P, *G = W + L.G;
+  const long long fS = p->totS * nU, f1I = p->totI * ns, f2I = p->totI * nU;
+  FRef Ub[2] = {FRef{W + L.Ub, nullptr}, FRef{W + L.Ub + fS, nullptr}};
+  auto F1p = [&](int slot) { return W + L.F1 + f1I * slot; };
+  auto F2p = [&](int slot) { return W + L.F2 + f2I * slot; };
+  // slots: 0 the step-start value, 1..M (1..M2) and M+1..2M (M2+1..2M2) the
+  // two sweeps' values; roles rotate by renaming
+  int s10 = 0, s20 = 0;
+  std::vector<int> s1A(M1 + 1), s1B(M1 + 1), s2A(M2 + 1), s2B(M2 + 1);
+  for (int m = 1; m <= M1; ++m) {
+    s1A[m] = m;
+    s1B[m] = M1 + m;
+  }
+  for (int q = 1; q <= M2; ++q) {
+    s2A[q] = q;
+    s2B[q] = M2 + q;
+  }
+  o->chem(l, Uuser, F1p(s10));
+  eval_rhs_g(o, l, Uuser, P, G, FRef{F2p(s20), nullptr}, RHS_AD);
+  std::vector<int> F1old(M1 + 1), F2old(M2 + 1), F1new(M1 + 1), F2new(M2 + 1);
+  for (int step = 0; step < nsteps; ++step) {
+    for (int j = 0; j <= M1; ++j) F1old[j] = s10;
+    for (int q = 0; q <= M2; ++q) F2old[q] = s20;
+    for (int k = 0; k < K; ++k) {
+      F1new[0] = s10;
+      F2new[0] = s20;
+      for (int m = 1; m <= M1; ++m) F1new[m] = (k % 2 == 0) ? s1A[m] : s1B[m];
+      for (int q = 1; q <= M2; ++q) F2new[q] = (k % 2 == 0) ? s2A[q] : s2B[q];
+      const bool last = step == nsteps - 1 && k == K - 1;
+      FRef Ucur = Uuser;
+      for (int pi = 0; pi < M1; ++pi) {
+        // implicit chemistry of the interval: c1, c2 = dt times the sums of
+        // the interval's S21 and S22 rows
+        Mr2Imp a{};
+        a.n1 = M1 + 1;
+        for (int j = 0; j <= M1; ++j) {
+          double sum = 0.0;
+          for (int q = pi * r; q < (pi + 1) * r; ++q) sum += S21[q][j];
+          a.F1[j] = F1p(F1old[j]);
+          a.c1[j] = dt * sum;
+        }
+        a.n2 = r + 1;
+        for (int jj = 0; jj <= r; ++jj) {
+          double sum = 0.0;
+          for (int q = pi * r; q < (pi + 1) * r; ++q) sum += S22[q][pi * r + jj];
+          a.F2[jj] = F2p(F2old[pi * r + jj]);
+          a.c2[jj] = dt * sum;
+        }
+        a.F1right = F1p(F1old[pi + 1]);
+        a.h = (double)(t1[pi + 1] - t1[pi]) * dt;
+        a.X = F1p(F1new[pi + 1]);
+        a.J = W + L.A;
+        o->mr2_imp(l, Ucur, a);
+        for (int q = pi * r; q < (pi + 1) * r; ++q) {
+          if (q > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{F2p(F2new[q]), nullptr}, RHS_AD, true);
+          const FRef Unext = (k == K - 1 && q == M2 - 1) ? Uuser : Ub[q % 2];
+          Mr2Node nd{};
+          nd.n2 = s->n_fine;
+          for (int j = 0; j < s->n_fine; ++j) {
+            nd.F2[j] = F2p(F2old[plo[q] + j]);
+            nd.S22[j] = S22[q][plo[q] + j];
+          }
+          nd.n1 = M1 + 1;
+          for (int j = 0; j <= M1; ++j) {
+            nd.F1[j] = F1p(F1old[j]);
+            nd.S21[j] = S21[q][j];
+          }
+          nd.F2new_q = F2p(F2new[q]);
+          nd.F2old_q = F2p(F2old[q]);
+          nd.X = F1p(F1new[pi + 1]);
+          nd.F1right = F1p(F1old[pi + 1]);
+          nd.dtq = (double)(t2[q + 1] - t2[q]) * dt;
+          nd.dt = dt;
+          o->mr2_node(l, Ucur, Unext, nd);
+          Ucur = Unext;
+        }
+      }
+      if (!last) eval_rhs_g(o, l, Ucur, P, G, FRef{F2p(F2new[M2]), nullptr}, RHS_AD, true);
+      F1old = F1new;
+      F2old = F2new;
+    }
+    if (step < nsteps - 1) {
+      // f2 of the end state (the last sweep's) by exchanging slot roles; f1
+      // of it evaluated afresh into the step-start slot
+      const int fin2 = F2new[M2];
+      for (int q = 1; q <= M2; ++q) {
+        if (s2A[q] == fin2) s2A[q] = s20;
+        if (s2B[q] == fin2) s2B[q] = s20;
+      }
+      s20 = fin2;
+      o->ghost(l, Uuser);
+      o->chem(l, Uuser, F1p(s10));
+    }
+  }
+  o->ghost(l, Uuser);
+  return SDC_OK;
+}
+
 int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sdc_scheme *s,
             void *ws, size_t ws_bytes, hipStream_t st) {
   const Ops *o = c->ops;
@@ -633,6 +791,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
   double *P = W + L.P, *G = W + L.G;
   const LaunchCtx l = make_lc(c, p, st);
   const long long fI = p->totI * nU, fS = p->totS * nU;
+  if (s->n_fine != 0 && s->mode == 2) return run_mrsdc2(c, p, Uuser, dt, nsteps, s, W, L, l);
   const int M = s->n_coarse - 1, K = s->sweeps;
   std::vector<long double> t = gauss_lobatto(s->n_coarse);
   if (s->n_fine == 0) {
@@ -1091,7 +1250,7 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
   int rc = get_plan(c, nbox, boxes, nbox > 1 ? U : nullptr, &pl);
   if (rc) return rc;
   FRef Uref = nbox > 1 ? FRef{nullptr, pl->d_Utab} : FRef{U[0], nullptr};
-  if (scheme->n_fine != 0) {
+  if (scheme->n_fine != 0 && scheme->mode != 2) {
     rc = fine_tables(c, scheme);
     if (rc) return rc;
   }
@@ -1107,10 +1266,12 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
   // the kernel variants (species count, stencil, species-diffusion form,
   // fine-sweep form)
   char buf[320];
-  snprintf(buf, sizeof buf, "|%p|%.17g|%d|%d,%d,%d,%d|%p|%zu|%p|ns%d|w%d|ref%d|ff%d|smc%d|%p", (void *)pl, dt,
-           nsteps, scheme->n_coarse, scheme->sweeps, scheme->n_fine, scheme->fine_repeat, workspace, ws_bytes,
-           nbox > 1 ? nullptr : (void *)U[0], c->ops->ns, (int)c->wide, c->h_mech.ref, (int)c->fused_fine,
-           (int)c->smc_stencil, scheme->n_fine != 0 ? (void *)c->d_fine : nullptr);
+  const bool tables = scheme->n_fine != 0 && scheme->mode != 2;
+  snprintf(buf, sizeof buf, "|%p|%.17g|%d|%d,%d,%d,%d,m%d|%p|%zu|%p|ns%d|w%d|ref%d|ff%d|smc%d|%p", (void *)pl,
+           dt, nsteps, scheme->n_coarse, scheme->sweeps, scheme->n_fine, scheme->fine_repeat,
+           scheme->mode == 2 ? 2 : 1, workspace, ws_bytes, nbox > 1 ? nullptr : (void *)U[0], c->ops->ns,
+           (int)c->wide, c->h_mech.ref, (int)c->fused_fine, (int)c->smc_stencil,
+           tables ? (void *)c->d_fine : nullptr);
   const std::string key = buf;
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
@@ -1296,7 +1457,7 @@ int last_status(sdc_context *c, void *stream) {
   if (e) {
     HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
     return fail(c, SDC_ETEMP, "device error flags " + std::to_string(e) +
-                                  " (1 Newton not converged, 2 T out of range, 4 rho <= 0)");
+                                  " (1 Newton not converged, 2 T out of range, 4 rho <= 0, 8 implicit chemistry not converged)");
   }
   return SDC_OK;
 }

@@ -1244,6 +1244,225 @@ __global__ __launch_bounds__(256, 2) void k_mr_fused(const BoxDev *__restrict__ 
 
 namespace nsdc {
 
+// ------------------------------------------------ multirate SDC, mode 2
+// Chemistry source w_k = W_k sum_j nu_kj q_j of the species densities y at
+// fixed rho and internal energy, and the Newton matrix of the implicit solve
+//   A = I - h dw/dy,
+// dw/dy from mass action (dq_j/dc_m) and the Arrhenius and equilibrium
+// temperature dependence (dq_j/dT) with the temperature following the
+// species at fixed internal energy: dT/dy_m = -e_m(T) / (rho c_v).  The
+// per-cell arrays live in the lane's workspace slot sl (entry i at sl[i st]):
+//   A [NS][NS] | y | b | G | c [NS+1] | g [NS+1] | h/RT [NS+1] | aT [NS+1] | w [NS+1]
+// (index NS of the last five is the dummy species of absent molecules).
+template <int NS>
+struct Mr2Slot {
+  double *p;
+  long long st;
+  static constexpr int A = 0, Y = NS * NS, B = Y + NS, G = B + NS, C = G + NS, GR = C + NS + 1,
+                       HR = GR + NS + 1, AT = HR + NS + 1, W = AT + NS + 1;
+  __device__ double &operator()(int i) const { return p[i * st]; }
+  __device__ double &a(int r, int c) const { return p[(r * NS + c) * st]; }
+};
+static_assert(Mr2Slot<21>::W + 22 == NSDC_MR2_SLOT(21), "mode-2 slot layout");
+
+template <int NS>
+__device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<NS> &sl, double rho, double T,
+                                   double cv, double h) {
+  const double lnT = log(T), invT = 1.0 / T;
+  for (int k = 0; k < NS; ++k) {
+    sl(sl.C + k) = sl(sl.Y + k) * m->invW[k];
+    sl(sl.GR + k) = g_RT(m, k, T, invT, lnT);
+    sl(sl.HR + k) = h_RT(m, k, T, invT);
+    sl(sl.AT + k) = 0.0;
+    sl(sl.W + k) = 0.0;
+    for (int c = 0; c < NS; ++c) sl.a(k, c) = 0.0;
+  }
+  sl(sl.C + NS) = 1.0;
+  sl(sl.GR + NS) = 0.0;
+  sl(sl.HR + NS) = 0.0;
+  sl(sl.AT + NS) = 0.0;
+  sl(sl.W + NS) = 0.0;
+  const double lnRTp = lnT + LN_RU_PREF;
+  const int nr = m->nr;
+  for (int j = 0; j < nr; ++j) {
+    const int sp[4] = {m->rs[j][0], m->rs[j][1], m->ps[j][0], m->ps[j][1]};
+    const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
+    const double dg = (sl(sl.GR + sp[2]) + sl(sl.GR + sp[3])) - (sl(sl.GR + sp[0]) + sl(sl.GR + sp[1]));
+    const double kf = exp(lnkf);
+    const double kr = exp(lnkf + dg + m->dnu[j] * lnRTp);
+    const double c0 = sl(sl.C + sp[0]), c1 = sl(sl.C + sp[1]), c2 = sl(sl.C + sp[2]), c3 = sl(sl.C + sp[3]);
+    const double fwd = kf * c0 * c1, rev = kr * c2 * c3;
+    const double q = fwd - rev;
+    // d ln k_f / dT and d ln k_r / dT (d(g/RT)/dT = -(h/RT)/T)
+    const double dlkf = (m->beta[j] + m->EaR[j] * invT) * invT;
+    const double ddg = -((sl(sl.HR + sp[2]) + sl(sl.HR + sp[3])) - (sl(sl.HR + sp[0]) + sl(sl.HR + sp[1]))) * invT;
+    const double dlkr = dlkf + ddg + m->dnu[j] * invT;
+    const double dqdT = fwd * dlkf - rev * dlkr;
+    // dq/dc of the four slots (a species twice gets both terms)
+    const double dq[4] = {kf * c1, kf * c0, -kr * c3, -kr * c2};
+    for (int i = 0; i < 4; ++i) {
+      const double sgn = i < 2 ? -1.0 : 1.0;
+      const int k = sp[i];
+      sl(sl.W + k) += sgn * q;
+      sl(sl.AT + k) += sgn * dqdT;
+      if (k < NS)
+        for (int l = 0; l < 4; ++l)
+          if (sp[l] < NS) sl.a(k, sp[l]) += sgn * dq[l] * m->invW[sp[l]];
+    }
+  }
+  // A = I - h W_k (d(sum nu q)/dy_m + aT_k dT/dy_m); w_k = W_k (sum nu q)_k
+  const double irc = 1.0 / (rho * cv);
+  for (int k = 0; k < NS; ++k) {
+    const double hW = h * m->W[k], aT = sl(sl.AT + k);
+    for (int c = 0; c < NS; ++c) {
+      const double dTdy = -m->Rk[c] * T * (sl(sl.HR + c) - 1.0) * irc;
+      sl.a(k, c) = (k == c ? 1.0 : 0.0) - hW * (sl.a(k, c) + aT * dTdy);
+    }
+    sl(sl.W + k) *= m->W[k];
+  }
+}
+
+// A x = G in place (x in G) by Gaussian elimination with partial pivoting.
+template <int NS>
+__device__ void mr2_solve(const Mr2Slot<NS> &sl) {
+  for (int col = 0; col < NS; ++col) {
+    int piv = col;
+    double best = fabs(sl.a(col, col));
+    for (int r = col + 1; r < NS; ++r) {
+      const double v = fabs(sl.a(r, col));
+      if (v > best) {
+        best = v;
+        piv = r;
+      }
+    }
+    if (piv != col) {
+      for (int c = col; c < NS; ++c) {
+        const double t = sl.a(col, c);
+        sl.a(col, c) = sl.a(piv, c);
+        sl.a(piv, c) = t;
+      }
+      const double t = sl(sl.G + col);
+      sl(sl.G + col) = sl(sl.G + piv);
+      sl(sl.G + piv) = t;
+    }
+    const double inv = 1.0 / sl.a(col, col);
+    for (int r = col + 1; r < NS; ++r) {
+      const double f = sl.a(r, col) * inv;
+      if (f != 0.0) {
+        for (int c = col + 1; c < NS; ++c) sl.a(r, c) -= f * sl.a(col, c);
+        sl(sl.G + r) -= f * sl(sl.G + col);
+      }
+    }
+  }
+  for (int r = NS - 1; r >= 0; --r) {
+    double x = sl(sl.G + r);
+    for (int c = r + 1; c < NS; ++c) x -= sl.a(r, c) * sl(sl.G + c);
+    sl(sl.G + r) = x / sl.a(r, r);
+  }
+}
+
+// Implicit chemistry of one coarse interval (Mr2Imp): per cell the state
+// U* = U_p + sum_j c1_j F1_j + sum_j c2_j F2_j - h F1_{p+1} (species part of
+// the F1 terms only), then Newton's method on y - h w(y) = b for its species
+// densities b (rho, rho u, rho E fixed, hence rho and the internal energy):
+// stop one iteration after the first whose largest update is at most
+// 1e-13 rho (at most 40; else NSDC_ERR_IMPLICIT).  Writes X = w(y*).
+template <int NS>
+__global__ __launch_bounds__(256) void k_mr2_imp(const BoxDev *__restrict__ boxes,
+                                                 const Item *__restrict__ items, int nitems, TileShape ts,
+                                                 FRef Ucur, Mr2Imp a, const DevMech *__restrict__ m, int *err) {
+  constexpr int NU = 5 + NS;
+  const Mr2Slot<NS> sl{a.J + (long long)blockIdx.x * blockDim.x + threadIdx.x, a.jstride};
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+    const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+    const long long i = ((long long)z * b.ny + y) * b.nx + x;
+    const long long o2 = b.offI * NU + i, o1 = b.offI * NS + i;
+    const double *U = Ucur.get(w.box, b.offS * NU);
+    double Us[5];
+    for (int q = 0; q < NU; ++q) {
+      double v = U[q * nS + s];
+      for (int j = 0; j < a.n2; ++j) v += a.c2[j] * a.F2[j][o2 + q * nI];
+      if (q >= 5) {
+        for (int j = 0; j < a.n1; ++j) v += a.c1[j] * a.F1[j][o1 + (q - 5) * nI];
+        v -= a.h * a.F1right[o1 + (q - 5) * nI];
+        sl(sl.B + q - 5) = v;
+        sl(sl.Y + q - 5) = v;
+      } else {
+        Us[q] = v;
+      }
+    }
+    const double rho = Us[0], ir = 1.0 / rho;
+    const double e = Us[4] * ir - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2] + Us[3] * Us[3]) * ir * ir;
+    double T = 1000.0, Y[NS];
+    int errs = rho > 0.0 ? 0 : NSDC_ERR_RHO;
+    bool conv = false, done = false;
+    for (int itn = 0; itn < 40 && !done; ++itn) {
+      for (int k = 0; k < NS; ++k) Y[k] = sl(sl.Y + k) * ir;
+      errs |= temperature<NS>(m, Y, e, T, T);
+      double cv = 0.0;
+      for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
+      mr2_rates_jacobian<NS>(m, sl, rho, T, cv, a.h);
+      for (int k = 0; k < NS; ++k) sl(sl.G + k) = sl(sl.Y + k) - a.h * sl(sl.W + k) - sl(sl.B + k);
+      mr2_solve<NS>(sl);
+      double dmax = 0.0;
+      for (int k = 0; k < NS; ++k) {
+        const double d = sl(sl.G + k);
+        sl(sl.Y + k) -= d;
+        dmax = fmax(dmax, fabs(d));
+      }
+      done = conv;
+      conv = !(dmax > 1e-13 * rho);   // (a NaN update never converges)
+    }
+    if (!done) errs |= NSDC_ERR_IMPLICIT;
+    for (int k = 0; k < NS; ++k) Y[k] = sl(sl.Y + k) * ir;
+    errs |= temperature<NS>(m, Y, e, T, T);
+    double cv = 0.0;
+    for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
+    mr2_rates_jacobian<NS>(m, sl, rho, T, cv, a.h);
+    for (int k = 0; k < NS; ++k) a.X[o1 + k * nI] = sl(sl.W + k);
+    if (errs) atomicOr(err, errs);
+  }
+}
+
+// Fine sub-step of eq. (mrupdate2) (Mr2Node).
+template <int NS>
+__global__ __launch_bounds__(256) void k_mr2_node(const BoxDev *__restrict__ boxes,
+                                                  const Item *__restrict__ items, int nitems, TileShape ts,
+                                                  FRef Ucur, FRef Unext, Mr2Node a) {
+  constexpr int NU = 5 + NS;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    int x, y, z;
+    tile_cell(w, ts, x, y, z);
+    if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+    const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+    const long long i = ((long long)z * b.ny + y) * b.nx + x;
+    const long long o2 = b.offI * NU + i, o1 = b.offI * NS + i;
+    const double *Uc = Ucur.get(w.box, b.offS * NU);
+    double *Un = Unext.get(w.box, b.offS * NU);
+    for (int q = 0; q < NU; ++q) {
+      const long long k2 = o2 + q * nI;
+      double sq = 0.0;
+      for (int j = 0; j < a.n2; ++j) sq += a.S22[j] * a.F2[j][k2];
+      double corr = a.dtq * (a.F2new_q[k2] - a.F2old_q[k2]);
+      if (q >= 5) {
+        const long long k1 = o1 + (q - 5) * nI;
+        for (int j = 0; j < a.n1; ++j) sq += a.S21[j] * a.F1[j][k1];
+        corr += a.dtq * (a.X[k1] - a.F1right[k1]);
+      }
+      Un[q * nS + s] = Uc[q * nS + s] + corr + a.dt * sq;
+    }
+  }
+}
+
 static inline int grid_for(int nitems, int cap) { return nitems < cap ? (nitems > 0 ? nitems : 1) : cap; }
 
 template <int NS>
@@ -1336,6 +1555,24 @@ struct Launch {
     hipLaunchKernelGGL(k_rows_max, dim3(2 * (5 + NS)), dim3(256), 0, c.stream, a.partial, nb, 2 * (5 + NS), a.out);
     prof_end(c.prof, K_SDC_RESID, c.stream);
   }
+  static void mr2_imp(const LaunchCtx &c, FRef Ucur, const Mr2Imp &a) {
+    // the lanes' workspace slots bound the grid
+    // the lanes' workspace slots bound the grid (the workspace holds
+    // NSDC_MR2_MAXWG workgroups of the interior tile)
+    const int grid = grid_for(grid_for(c.nI, c.cap), NSDC_MR2_MAXWG), block = c.tsI.tx * c.tsI.ty * c.tsI.tz;
+    Mr2Imp b = a;
+    b.jstride = (long long)grid * block;
+    prof_begin(c.prof, K_MR2_IMP, c.stream);
+    hipLaunchKernelGGL(k_mr2_imp<NS>, dim3(grid), dim3(block), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Ucur,
+                       b, c.mech, c.err);
+    prof_end(c.prof, K_MR2_IMP, c.stream);
+  }
+  static void mr2_node(const LaunchCtx &c, FRef Ucur, FRef Unext, const Mr2Node &a) {
+    prof_begin(c.prof, K_SDC_NODE, c.stream);
+    hipLaunchKernelGGL(k_mr2_node<NS>, dim3(grid_for(c.nI, c.cap)), dim3(c.tsI.tx * c.tsI.ty * c.tsI.tz), 0,
+                       c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Ucur, Unext, a);
+    prof_end(c.prof, K_SDC_NODE, c.stream);
+  }
   static void mr_fine(const LaunchCtx &c, FRef Uin, FRef Uout, const FineCoef *fc,
                       const FinePtrs &fp, double *A, long long aslot) {
     const dim3 grid(grid_for(c.nI, c.cap)), block(c.tsI.tx * c.tsI.ty * c.tsI.tz);
@@ -1385,6 +1622,8 @@ static const Ops make_ops() {
   o.sdc_node = &Launch<NS>::sdc_node;
   o.sdc_resid = &Launch<NS>::sdc_resid;
   o.mr_fine = &Launch<NS>::mr_fine;
+  o.mr2_imp = &Launch<NS>::mr2_imp;
+  o.mr2_node = &Launch<NS>::mr2_node;
   return o;
 }
 static const Ops OPS9 = make_ops<9>();

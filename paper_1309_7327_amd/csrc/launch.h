@@ -10,7 +10,7 @@ namespace nsdc {
 enum KernelId {
   K_PRIM_TO_CONS = 0, K_GHOST, K_PRIMS, K_VGRAD, K_DIR_X, K_DIR_Y, K_DIR_Z, K_CHEM, K_SDC_NODE,
   K_MR_FINE, K_MR_SRC, K_DIR_ADJ_X, K_DIR_ADJ_Y, K_DIR_ADJ_Z, K_CHEM_ADJ, K_VGRAD_ADJ, K_PRIMS_ADJ,
-  K_FOLD, K_ADJ_LINALG, K_SDC_RESID, K_NKERNELS
+  K_FOLD, K_ADJ_LINALG, K_SDC_RESID, K_MR2_IMP, K_NKERNELS
 };
 struct Profiler;
 // Record a HIP event on `s` before (begin) / after (end) a launch of kernel `id`
@@ -55,6 +55,8 @@ struct Ops {
   void (*sdc_node)(const LaunchCtx &, FRef, FRef, const NodeArgs &);
   void (*sdc_resid)(const LaunchCtx &, FRef U0, FRef UM, const ResidArgs &);
   void (*mr_fine)(const LaunchCtx &, FRef, FRef, const FineCoef *, const FinePtrs &, double *, long long);
+  void (*mr2_imp)(const LaunchCtx &, FRef, const Mr2Imp &);
+  void (*mr2_node)(const LaunchCtx &, FRef, FRef, const Mr2Node &);
 };
 
 // nullptr for an unsupported species count

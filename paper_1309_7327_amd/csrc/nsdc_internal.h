@@ -13,6 +13,7 @@
 #define NSDC_ERR_NEWTON 1
 #define NSDC_ERR_TRANGE 2
 #define NSDC_ERR_RHO 4
+#define NSDC_ERR_IMPLICIT 8   // implicit chemistry (multirate mode 2): Newton did not converge
 
 // Mechanism tables in device memory.  Thermodynamic polynomials are stored
 // pre-scaled for Horner evaluation of c_p/R, h/(RT) and s/R; reactions as
@@ -120,4 +121,43 @@ struct FinePtrs {
   int nq;          // fine sub-steps of the interval (the same as the coefficient table's)
   int n1;          // coarse nodes (the same as the coefficient table's)
   double dt;
+};
+
+// Multirate SDC mode 2 (eq. mrupdate2): the chemistry f1 on the coarse nodes
+// (ns components per cell), advection-diffusion f2 on the fine nodes (nU).
+//
+// Implicit solve of one coarse interval p: per cell, y - h w(y) = b for the
+// species densities, b the species part of
+//   U_p + sum_j c1_j F1_j + sum_j c2_j F2_j - h F1_{p+1}
+// (c1, c2: dt times the interval's sums of S21 and S22 rows), h the coarse
+// interval; the other components are those of the same sum.  X = w(y*).
+// Each lane owns a slot of the workspace J (entry i at J[lane + i jstride],
+// NSDC_MR2_SLOT(ns) entries) for its Newton matrix and vectors.
+#define NSDC_MR2_SLOT(ns) ((ns) * (ns) + 8 * (ns) + 5)
+#define NSDC_MR2_MAXWG 512   // workgroups of the implicit kernel (the lane slots)
+struct Mr2Imp {
+  const double *F1[8];              // f1 at the coarse nodes, iteration k
+  double c1[8];
+  const double *F2[NSDC_MAXFINE];   // f2 at the interval's fine nodes, iteration k
+  double c2[NSDC_MAXFINE];
+  int n1, n2;
+  const double *F1right;            // f1 at node p+1, iteration k
+  double h;
+  double *X;                        // out: f1 at node p+1, iteration k+1
+  double *J;
+  long long jstride;
+};
+
+// Fine sub-step q of eq. (mrupdate2):
+//   U_{q+1} = U_q + dtq (X - F1_{p+1}) + dtq (F2new_q - F2old_q)
+//             + dt (sum_j S22_qj F2old_j + sum_j S21_qj F1old_j)
+struct Mr2Node {
+  const double *F2[9];   // f2 (iteration k) at the nodes of sub-step q's fine piece
+  double S22[9];
+  int n2;
+  const double *F1[8];   // f1 (iteration k) at the coarse nodes
+  double S21[8];
+  int n1;
+  const double *F2new_q, *F2old_q, *X, *F1right;
+  double dtq, dt;
 };

@@ -41,7 +41,7 @@ class MechanismDesc(ctypes.Structure):
 
 class Scheme(ctypes.Structure):
     _fields_ = [("n_coarse", ctypes.c_int), ("sweeps", ctypes.c_int), ("n_fine", ctypes.c_int),
-                ("fine_repeat", ctypes.c_int)]
+                ("fine_repeat", ctypes.c_int), ("mode", ctypes.c_int)]
 
 
 _vp, _ip, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -98,8 +98,8 @@ def box(nx, ny, nz, dx, dy=None, dz=None):
     return BoxDesc(nx, ny, nz, NG, dx, dx if dy is None else dy, dx if dz is None else dz)
 
 
-def scheme(n_coarse=4, sweeps=6, n_fine=0, fine_repeat=1):
-    return Scheme(n_coarse, sweeps, n_fine, fine_repeat)
+def scheme(n_coarse=4, sweeps=6, n_fine=0, fine_repeat=1, mode=1):
+    return Scheme(n_coarse, sweeps, n_fine, fine_repeat, mode)
 
 
 def _stream(stream):

@@ -3,6 +3,10 @@ text records kept under profiles/.
 
   python -m paper_1309_7327_amd.rocpd_summary kernels DB --title TEXT --command CMD
       per-kernel calls / total / average duration (markdown, stdout)
+  python -m paper_1309_7327_amd.rocpd_summary fp64 DB --title TEXT --command CMD
+      per-kernel FP64 VALU instruction counts (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64,
+      one run) and the FP64 rate they give over the dispatch durations of
+      the same run, against the 78.6 TFLOP/s vector peak (markdown, stdout)
   python -m paper_1309_7327_amd.rocpd_summary traffic --fetch DB --write DB --workload NAME
         --out-dir DIR --command-fetch CMD --command-write CMD
       HBM bytes per launch of every library kernel from a FETCH_SIZE run and
@@ -27,7 +31,8 @@ CALIB_BYTES = 1 << 30
 _KINDS = [
     (r"k_prim_to_cons<", "prim_to_cons"), (r"k_ghost<", "ghost"), (r"k_prims<", "prims"),
     (r"k_vgrad<", "vgrad"), (r"k_dir<\d+, 0", "dir_x"), (r"k_dir<\d+, 1", "dir_y"), (r"k_dir<\d+, 2", "dir_z"),
-    (r"k_chem<", "chem"), (r"k_sdc_node<", "sdc_node"), (r"k_mr_step<", "mr_fine"), (r"k_mr_fused<", "mr_fine"), (r"k_mr_src<", "mr_src"),
+    (r"k_chem<", "chem"), (r"k_sdc_node<", "sdc_node"), (r"k_mr_step<", "mr_fine"), (r"k_mr_fused<", "mr_fine"), (r"k_mr_pair<", "mr_fine"),
+    (r"k_mr_src<", "mr_src"), (r"k_mr2_imp<", "mr2_imp"), (r"k_mr2_node<", "sdc_node"),
     (r"k_adj_(coef|g1|g2|g3)<\d+, 0", "dir_adj_x"), (r"k_adj_(coef|g1|g2|g3)<\d+, 1", "dir_adj_y"),
     (r"k_adj_(coef|g1|g2|g3)<\d+, 2", "dir_adj_z"),
     (r"k_chem_adj<", "chem_adj"), (r"k_vgrad_adj<", "vgrad_adj"), (r"k_prims_adj<", "prims_adj"),
@@ -79,6 +84,34 @@ def counters(db, counter):
         if cname == counter:
             out[name].append(val)
     return out
+
+
+FP64_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                 "SQ_INSTS_VALU_TRANS_F64")
+FP64_PEAK = 78.6e12
+
+
+def fp64_table(db):
+    """Per kernel: dispatches, mean duration (ns), mean wave instruction count
+    per FP64 counter, and FLOP/s = 64 lanes x (ADD + MUL + 2 FMA + TRANS)
+    per dispatch / duration (every lane of a wave counted active)."""
+    con = sqlite3.connect(db)
+    acc = collections.OrderedDict()
+    for name, cname, val, t0, t1, did in con.execute(
+            "select kernel_name, counter_name, value, start, end, dispatch_id from counters_collection"):
+        if cname not in FP64_COUNTERS:
+            continue
+        a = acc.setdefault(short_name(name), {"disp": {}, "cnt": collections.defaultdict(float)})
+        a["disp"][did] = t1 - t0
+        a["cnt"][cname] += val
+    rows = []
+    for k, a in acc.items():
+        n = len(a["disp"])
+        dur = sum(a["disp"].values()) / n
+        c = {cn: a["cnt"][cn] / n for cn in FP64_COUNTERS}
+        fl = 64.0 * (c[FP64_COUNTERS[0]] + c[FP64_COUNTERS[1]] + 2.0 * c[FP64_COUNTERS[2]] + c[FP64_COUNTERS[3]])
+        rows.append((k, n, dur, c, fl, fl / (dur * 1e-9) if dur > 0 else 0.0))
+    return sorted(rows, key=lambda r: -r[2] * r[1])
 
 
 def traffic(fetch_db, write_db, workload, out_dir, cmd_fetch, cmd_write):
@@ -133,6 +166,10 @@ def main():
     k.add_argument("db")
     k.add_argument("--title", default="kernel trace")
     k.add_argument("--command", default="")
+    f = sub.add_parser("fp64")
+    f.add_argument("db")
+    f.add_argument("--title", default="FP64 instruction counts")
+    f.add_argument("--command", default="")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -149,6 +186,21 @@ def main():
         print("| kernel | calls | total ns | average ns | % |\n|---|---:|---:|---:|---:|")
         for name, n, tot, avg, pct in kernel_table(a.db):
             print(f"| {name} | {n} | {tot:.0f} | {avg:.0f} | {pct:.2f} |")
+    elif a.cmd == "fp64":
+        print(f"# {a.title}\n")
+        if a.command:
+            print("Command (from the repository root):\n\n```\n" + a.command + "\n```\n")
+        print(f"Kernel sources hash {source_hash()}. Wave-level instruction counts per dispatch (means); "
+              "FLOP per dispatch = 64 x (ADD + MUL + 2 FMA + TRANS); rate over the dispatch durations of "
+              "the same counter run; peak 78.6 TFLOP/s (FP64 vector).\n")
+        print("| kernel | dispatches | avg ms | ADD_F64 | MUL_F64 | FMA_F64 | TRANS_F64 | GFLOP / dispatch "
+              "| TFLOP/s | of peak |\n|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
+        for k, n, dur, c, fl, rate in fp64_table(a.db):
+            if fl == 0.0:
+                continue
+            print(f"| {k} | {n} | {dur * 1e-6:.3f} | {c[FP64_COUNTERS[0]]:.4g} | {c[FP64_COUNTERS[1]]:.4g} | "
+                  f"{c[FP64_COUNTERS[2]]:.4g} | {c[FP64_COUNTERS[3]]:.4g} | {fl * 1e-9:.3f} | {rate * 1e-12:.2f} | "
+                  f"{100.0 * rate / FP64_PEAK:.1f}% |")
     else:
         traffic(a.fetch, a.write, a.workload, a.out_dir, a.command_fetch, a.command_write)
 

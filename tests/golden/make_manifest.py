@@ -9,8 +9,10 @@ forward-Euler sub-steps of the largest time step used with the mechanism are
 stable (rate * 2 * DT_MAX <= 0.5).  The rate constants come from the oracle.
 
 It then fixes each workload's time step from the oracle's thermodynamics:
-dt = 0.1 min(dx) / max over cells of (|u|_max + c), c the sound speed of the
-initial state, capped at DT_MAX.
+dt = cfl min(dx) / max over cells of (|u|_max + c), c the sound speed of the
+initial state, cfl = 0.1 (capped at DT_MAX) unless the workload names its
+own (the implicit-chemistry workload: not capped, its chemistry is not
+sub-stepped explicitly).
 
 Run:  python tests/golden/make_manifest.py
 """
@@ -59,14 +61,14 @@ def screen(kind, seed):
     raise RuntimeError(f"{kind}: only {len(chosen)} of {nr} reactions pass the screen")
 
 
-def sound_speed_dt(om, prims, dx):
-    """0.1 min(dx) / max(|u_i| + c) over every cell of every box."""
+def sound_speed_dt(om, prims, dx, cfl=0.1):
+    """cfl min(dx) / max(|u_i| + c) over every cell of every box."""
     speed = 0.0
     for prim in prims:
         U = oracle.prim_to_cons(om, prim)
         c = oracle.sound_speed(om, U)
         speed = max(speed, float(np.max(np.abs(prim["u"]).max(axis=0) + c)))
-    return 0.1 * float(np.min(dx)) / speed
+    return cfl * float(np.min(dx)) / speed
 
 
 def main():
@@ -83,7 +85,10 @@ def main():
         om = oracle.Mechanism(m)
         prims = make_primitives(name, m)
         prims = prims if isinstance(prims, list) else [prims]
-        dt = min(sound_speed_dt(om, prims, wl["dx"]), DT_MAX)
+        if "cfl" in wl:
+            dt = sound_speed_dt(om, prims, wl["dx"], wl["cfl"])
+        else:
+            dt = min(sound_speed_dt(om, prims, wl["dx"]), DT_MAX)
         dts[name] = dt
         print(name, "dt", dt)
     with open(os.path.join(OUT, "dt.json"), "w") as f:
