@@ -45,6 +45,7 @@ class _OMech(ctypes.Structure):
         ("Pr", ctypes.c_double), ("bulk_ratio", ctypes.c_double),
         ("m47", ctypes.c_double), ("m48", ctypes.c_double),
         ("ref_species", ctypes.c_int), ("wide_stencil", ctypes.c_int),
+        ("nonperiodic", ctypes.c_int),
     ]
 
 
@@ -64,6 +65,10 @@ def lib():
         L.oracle_narrow_matrix.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         L.oracle_narrow6_matrix.argtypes = [ctypes.c_double, dp]
         L.oracle_d1_periodic.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
+        L.oracle_d1_line.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_narrow_line.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, dp]
+        L.oracle_narrow4_matrix.argtypes = [dp]
         L.oracle_narrow_periodic.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, dp]
         L.oracle_heat2d.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double,
@@ -102,9 +107,10 @@ class Mechanism:
     ref_species: -1 for the correction-velocity form of the species
     diffusion, k >= 0 for reference species k (Section 2.1).  wide: the
     wide stencil D(a D u) instead of the narrow one for the second-derivative
-    terms (Section 2.2)."""
+    terms (Section 2.2).  nonperiodic: bit d set for physical boundaries at
+    both ends of direction d, with the boundary stencils of Section 2.5."""
 
-    def __init__(self, mech, ref_species=-1, wide=False):
+    def __init__(self, mech, ref_species=-1, wide=False, nonperiodic=0):
         self.mech = mech
         self.ns = int(mech["ns"])
         self.nr = int(mech["nr"])
@@ -119,9 +125,10 @@ class Mechanism:
             _ptr(k["A"]).value, _ptr(k["b"]).value, _ptr(k["Ea"]).value,
             _ptr(k["nu_f"]).value, _ptr(k["nu_r"]).value, _ptr(k["Le"]).value,
             mech["mu_ref"], mech["T_ref"], mech["mu_exp"], mech["Pr"], mech["bulk_ratio"],
-            mech["m47"], mech["m48"], int(ref_species), int(bool(wide)))
+            mech["m47"], mech["m48"], int(ref_species), int(bool(wide)), int(nonperiodic))
         self.ref_species = int(ref_species)
         self.wide = bool(wide)
+        self.nonperiodic = int(nonperiodic)
 
     @property
     def ref(self):
@@ -154,6 +161,29 @@ def d1_point(f9, dx):
 def narrow_point(a9, u9, dx, m47, m48):
     a9, u9 = _f64(a9), _f64(u9)
     return lib().oracle_narrow_point(_ptr(a9), _ptr(u9), dx, m47, m48)
+
+
+def narrow4_matrix():
+    M = np.zeros((4, 4))
+    lib().oracle_narrow4_matrix(_ptr(M))
+    return M
+
+
+def d1_line(f, dx, kind):
+    """First derivative on a line with physical boundaries at both ends
+    (kind 0 advection, 1 diffusion closures)."""
+    f = _f64(f)
+    out = np.zeros_like(f)
+    lib().oracle_d1_line(len(f), _ptr(f), dx, int(kind), _ptr(out))
+    return out
+
+
+def narrow_line(a, u, dx, m47, m48):
+    """d/dx(a du/dx) on a line with physical boundaries at both ends."""
+    a, u = _f64(a), _f64(u)
+    out = np.zeros_like(u)
+    lib().oracle_narrow_line(len(u), _ptr(a), _ptr(u), dx, m47, m48, _ptr(out))
+    return out
 
 
 def d1_periodic(f, dx):

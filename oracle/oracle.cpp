@@ -112,6 +112,107 @@ S narrow(const S *a, const S *u, double dx, const double M[8][8]) {
   return (hp - hm) / (dx * dx);
 }
 
+// ------------------------------------------------ physical boundaries
+// Near a non-periodic boundary (Section 2.5) the stencils along its normal
+// drop in order with the distance b of the cell from the boundary (b = 0 for
+// the boundary cell itself):
+//   b >= 4  the eighth-order stencils above;
+//   b = 3   sixth-order centred first derivative and the sixth-order narrow
+//           stencil (the matrix of Section 2.2 with m36 = 281/3600);
+//   b = 2   fourth-order centred first derivative and the fourth-order
+//           member of the narrow family (narrow4 below);
+//   b = 1   advection: third-order first derivative biased away from the
+//           boundary; diffusion: second-order centred (first derivative
+//           (f_{i+1} - f_{i-1})/2h, second derivative with faces
+//           H_{i+1/2} = (a_i + a_{i+1})(u_{i+1} - u_i)/2);
+//   b = 0   advection: one-sided third-order first derivative; diffusion:
+//           one-sided second-order (first derivative (-3f_0 + 4f_1 - f_2)/2h,
+//           and (a u')' = a u'' + a' u' with the one-sided second-order u''
+//           (2u_0 - 5u_1 + 4u_2 - u_3)/h^2 and first derivatives).
+// The same formulas serve the high side mirrored (x -> -x).  Samples are
+// nine values f[0..8] centred on the cell (index 4); those beyond the
+// boundary are never used.
+enum Kind { ADVECTION = 0, DIFFUSION = 1 };
+
+// Fourth-order member of the narrow family: rows/cols 1..4 <-> offsets -1..2,
+// exact for deg a + deg u <= 5, the corner entries zero as in the
+// sixth-order matrix; one free parameter m33, set to 1/72 (it zeroes the
+// a term of the h^4 truncation error; every value in [1/72, 1/24]
+// minimises the sum of the absolute truncation coefficients).
+void narrow4(double M[4][4]) {
+  const double m33 = 1.0 / 72.0;
+  const double rows[4][4] = {
+      {-m33, 2.0 * m33 + 1.0 / 12.0, -m33 - 1.0 / 12.0, 0.0},
+      {2.0 * m33 + 1.0 / 12.0, -3.0 * m33 - 3.0 / 4.0, 2.0 / 3.0, m33},
+      {-m33, -2.0 / 3.0, 3.0 * m33 + 3.0 / 4.0, -2.0 * m33 - 1.0 / 12.0},
+      {0.0, m33 + 1.0 / 12.0, -2.0 * m33 - 1.0 / 12.0, m33},
+  };
+  std::memcpy(M, rows, sizeof(rows));
+}
+
+// first derivative at the centre of f[0..8] for a cell at distance b from a
+// boundary on side `high` (0: the boundary is below, 1: above)
+template <class S>
+S d1_bnd(const S *f, double dx, int b, int high, Kind kind) {
+  if (b >= 4) return d1(f, dx);
+  // mirror so that the boundary is below: g[o] = f[4 + o] (low) or -f[4 - o]
+  S g[9];
+  for (int o = -4; o <= 4; ++o) g[o + 4] = high ? S(-1.0) * f[4 - o] : f[4 + o];
+  S r;
+  if (b == 3)
+    r = 3.0 / 4.0 * (g[5] - g[3]) - 3.0 / 20.0 * (g[6] - g[2]) + 1.0 / 60.0 * (g[7] - g[1]);
+  else if (b == 2)
+    r = 2.0 / 3.0 * (g[5] - g[3]) - 1.0 / 12.0 * (g[6] - g[2]);
+  else if (b == 1)   // (written with differences, so a constant gives exactly 0)
+    r = kind == ADVECTION ? (-2.0 * (g[3] - g[4]) + 6.0 * (g[5] - g[4]) - (g[6] - g[4])) / 6.0
+                          : (g[5] - g[3]) / 2.0;
+  else
+    r = kind == ADVECTION ? (18.0 * (g[5] - g[4]) - 9.0 * (g[6] - g[4]) + 2.0 * (g[7] - g[4])) / 6.0
+                          : (4.0 * (g[5] - g[4]) - (g[6] - g[4])) / 2.0;
+  return r / dx;
+}
+
+// d/dx (a du/dx) at the centre of nine samples near a boundary
+template <class S>
+S narrow_bnd(const S *a, const S *u, double dx, int b, int high, const double M8[8][8]) {
+  if (b >= 4) return narrow(a, u, dx, M8);
+  // mirror so that the boundary is below (the operator is even in x)
+  S A[9], U[9];
+  for (int o = 0; o < 9; ++o) {
+    A[o] = high ? a[8 - o] : a[o];
+    U[o] = high ? u[8 - o] : u[o];
+  }
+  S hp = 0.0, hm = 0.0;
+  if (b == 3) {
+    double M[6][6];
+    narrow6(281.0 / 3600.0, M);
+    for (int m = -2; m <= 3; ++m)
+      for (int n = -2; n <= 3; ++n) {
+        hp = hp + A[4 + m] * M[m + 2][n + 2] * U[4 + n];
+        hm = hm + A[3 + m] * M[m + 2][n + 2] * U[3 + n];
+      }
+  } else if (b == 2) {
+    double M[4][4];
+    narrow4(M);
+    for (int m = -1; m <= 2; ++m)
+      for (int n = -1; n <= 2; ++n) {
+        hp = hp + A[4 + m] * M[m + 1][n + 1] * U[4 + n];
+        hm = hm + A[3 + m] * M[m + 1][n + 1] * U[3 + n];
+      }
+  } else if (b == 1) {
+    hp = 0.5 * (A[4] + A[5]) * (U[5] - U[4]);
+    hm = 0.5 * (A[3] + A[4]) * (U[4] - U[3]);
+  } else {
+    // 2u_0 - 5u_1 + 4u_2 - u_3, (-3u_0 + 4u_1 - u_2)/2 and the same for a,
+    // with differences from the boundary sample
+    const S u2 = -5.0 * (U[5] - U[4]) + 4.0 * (U[6] - U[4]) - (U[7] - U[4]);
+    const S u1 = (4.0 * (U[5] - U[4]) - (U[6] - U[4])) / 2.0;
+    const S a1 = (4.0 * (A[5] - A[4]) - (A[6] - A[4])) / 2.0;
+    return (A[4] * u2 + a1 * u1) / (dx * dx);
+  }
+  return (hp - hm) / (dx * dx);
+}
+
 // ------------------------------------------------------------ mechanism
 struct Mech {
   int ns, nr;
@@ -120,6 +221,7 @@ struct Mech {
   double Tlo, Thi, mu_ref, T_ref, mu_exp, Pr, bulk;
   int ref;   // -1 correction velocity, else the reference species
   int wide;  // 1: wide stencil D(a D u) for the second-derivative pairs
+  int np;    // bit d: physical (non-periodic) boundaries along direction d
   double M[8][8];
   explicit Mech(const omech *m)
       : ns(m->ns), nr(m->nr), W(m->W, m->W + m->ns), nasa(m->nasa, m->nasa + 7 * m->ns),
@@ -127,7 +229,7 @@ struct Mech {
         Le(m->Le, m->Le + m->ns), nuf(m->nu_f, m->nu_f + m->nr * m->ns),
         nur(m->nu_r, m->nu_r + m->nr * m->ns), Tlo(m->Tlo), Thi(m->Thi), mu_ref(m->mu_ref),
         T_ref(m->T_ref), mu_exp(m->mu_exp), Pr(m->Pr), bulk(m->bulk_ratio), ref(m->ref_species),
-        wide(m->wide_stencil) {
+        wide(m->wide_stencil), np(m->nonperiodic) {
     narrow8(m->m47, m->m48, M);
   }
 };
@@ -260,6 +362,7 @@ void production(const Mech &m, S rho, S T, const S *Y, const S *dlnA, S *wdot) {
 template <class S>
 struct Grid {
   int nx, ny, nz, sx, sy, sz, ns, nU;
+  int np = 0;   // bit d: physical boundaries along d
   double dx[3];
   std::vector<S> U;                       // ghosted conserved state
   std::vector<S> rho, T, p, mu, lam, xi;  // primitives on the ghost grid
@@ -280,13 +383,23 @@ int setup_grid(const Mech &m, int nx, int ny, int nz, const double *dxs, const S
   g.ns = m.ns; g.nU = 5 + m.ns;
   for (int d = 0; d < 3; ++d) g.dx[d] = dxs[d];
   const long n = g.n(), nin = long(nx) * ny * nz;
+  g.np = m.np;
+  // physical boundaries: at least 8 cells between them, narrow stencil only
+  if (m.np && m.wide) return -1;
+  const int dims[3] = {nx, ny, nz};
+  for (int d = 0; d < 3; ++d)
+    if (((m.np >> d) & 1) && dims[d] < 8) return -1;
   g.U.assign(long(g.nU) * n, S(0.0));
+  // ghost layers: periodic images, or along a direction with physical
+  // boundaries copies of the nearest boundary cell (never used by the
+  // boundary stencils; they only keep the ghost primitives finite)
+  auto gi = [&](int i, int nn, int d) { return (m.np >> d) & 1 ? std::min(std::max(i, 0), nn - 1) : wrap(i, nn); };
   for (int c = 0; c < g.nU; ++c)
     for (int k = -NG; k < nz + NG; ++k)
       for (int j = -NG; j < ny + NG; ++j)
         for (int i = -NG; i < nx + NG; ++i)
           g.U[c * n + g.at(i, j, k)] =
-              Uin[c * nin + (long(wrap(k, nz)) * ny + wrap(j, ny)) * nx + wrap(i, nx)];
+              Uin[c * nin + (long(gi(k, nz, 2)) * ny + gi(j, ny, 1)) * nx + gi(i, nx, 0)];
   g.rho.resize(n); g.T.resize(n); g.p.resize(n); g.mu.resize(n); g.lam.resize(n); g.xi.resize(n);
   for (int d = 0; d < 3; ++d) g.u[d].resize(n);
   g.Y.resize(long(m.ns) * n); g.X.resize(long(m.ns) * n);
@@ -334,17 +447,33 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
   const long c0 = g.at(i, j, k);
   // stored index of the cell s steps along direction d (periodic images:
   // the wide operator reaches 8 cells, past the 4 ghost layers)
+  // along a direction with physical boundaries: the cell's distance bd from
+  // the nearer boundary and which one it is (the stencils of d1_bnd and
+  // narrow_bnd); samples past the boundary are clamped copies, never used
+  const int cc[3] = {i, j, k}, nn[3] = {g.nx, g.ny, g.nz};
+  int bd[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    const bool phys = (g.np >> d) & 1;
+    bd[d] = phys ? std::min(cc[d], nn[d] - 1 - cc[d]) : 4;
+    hi[d] = phys && (nn[d] - 1 - cc[d] < cc[d]);
+  }
   auto pt = [&](int d, int s) {
     int ii = i, jj = j, kk = k;
-    if (d == 0) ii = wrap(i + s, g.nx); else if (d == 1) jj = wrap(j + s, g.ny); else kk = wrap(k + s, g.nz);
+    auto mv = [&](int c, int n) { return (g.np >> d) & 1 ? std::min(std::max(c + s, 0), n - 1) : wrap(c + s, n); };
+    if (d == 0) ii = mv(i, g.nx); else if (d == 1) jj = mv(j, g.ny); else kk = mv(k, g.nz);
     return g.at(ii, jj, kk);
   };
-  // D_jdir u_comp at stored index c (c must have 4 neighbours along jdir)
+  // first derivatives along d of advective and diffusive terms
+  auto dA = [&](const S *f, int d) { return d1_bnd(f, g.dx[d], bd[d], hi[d], ADVECTION); };
+  auto dD = [&](const S *f, int d) { return d1_bnd(f, g.dx[d], bd[d], hi[d], DIFFUSION); };
+  // D_jdir u_comp at stored index c, a cell on the line through the output
+  // cell along another direction (so its position along jdir is the output
+  // cell's; c has 4 neighbours or their clamped copies along jdir)
   auto grad = [&](long c, int jdir, int comp) {
     long stride = jdir == 0 ? 1 : (jdir == 1 ? g.sx : long(g.sx) * g.sy);
     S f[9];
     for (int s = -4; s <= 4; ++s) f[s + 4] = g.u[comp][c + s * stride];
-    return d1(f, g.dx[jdir]);
+    return dD(f, jdir);
   };
   // second-derivative pairs L_d(a, u): a and u sampled at s = -R..R (index
   // s + 8); narrow stencil (eq. H) from s = -4..4, or with the wide stencil
@@ -352,8 +481,9 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
   // derivative of u, which reaches s = -8..8 (Section 2.2)
   S f[9], a[17], uu[17];
   const int R = m.wide ? 8 : 4;
+  int dcur = 0;   // direction of the pairs being summed
   auto pair = [&](const S *aa, const S *uv, double h) -> S {
-    if (!m.wide) return narrow(aa + 4, uv + 4, h, m.M);
+    if (!m.wide) return narrow_bnd(aa + 4, uv + 4, h, bd[dcur], hi[dcur], m.M);
     S g9[9];
     for (int o = -4; o <= 4; ++o) g9[o + 4] = aa[o + 8] * d1(uv + o + 4, h);
     return d1(g9, h);
@@ -372,7 +502,7 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
           else fl = g.U[q * n + c] * ud;
           f[s + 4] = fl;
         }
-        out[q] = out[q] - d1(f, g.dx[d]);
+        out[q] = out[q] - dA(f, d);
       }
     }
   }
@@ -383,6 +513,7 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
     std::vector<S> DY(3 * ns), DhY(3 * ns);
     for (int d = 0; d < 3; ++d) {
       const double h = g.dx[d];
+      dcur = d;
       // viscous momentum terms
       for (int ic = 0; ic < 3; ++ic) {
         for (int s = -R; s <= R; ++s) {
@@ -419,7 +550,7 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
           long c = pt(d, s);
           f[s + 4] = g.mu[c] * grad(c, ic, d);
         }
-        out[1 + ic] = out[1 + ic] + d1(f, h);
+        out[1 + ic] = out[1 + ic] + dD(f, d);
       }
       for (int s = -4; s <= 4; ++s) {
         long c = pt(d, s);
@@ -428,7 +559,7 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
           if (jd != d) divt = divt + grad(c, jd, jd);
         f[s + 4] = (g.xi[c] - 2.0 / 3.0 * g.mu[c]) * divt;
       }
-      out[1 + d] = out[1 + d] + d1(f, h);
+      out[1 + d] = out[1 + d] + dD(f, d);
       for (int s = -4; s <= 4; ++s) {
         long c = pt(d, s);
         S t1 = 0.0, divt = 0.0;
@@ -439,7 +570,7 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
         }
         f[s + 4] = g.mu[c] * t1 + (g.xi[c] - 2.0 / 3.0 * g.mu[c]) * g.u[d][c] * divt;
       }
-      out[4] = out[4] + d1(f, h);
+      out[4] = out[4] + dD(f, d);
       if (m.ref >= 0) {
         // reference species (Section 2.1): species k != ref carry the mixture
         // model flux Fbar_k, the reference species carries -sum of them, and
@@ -517,19 +648,19 @@ void rhs_cell(const Mech &m, const Grid<S> &g, int i, int j, int k, unsigned par
       out[4] = out[4] + pair(a, uu, h);
       // correction velocity component d, first derivatives of Y_k and h_k Y_k
       for (int s = -4; s <= 4; ++s) f[s + 4] = g.p[pt(d, s)];
-      S Dp = d1(f, h);
+      S Dp = dD(f, d);
       S vc = 0.0;
       for (int ks = 0; ks < ns; ++ks) {
         for (int s = -4; s <= 4; ++s) f[s + 4] = g.X[ks * n + pt(d, s)];
-        S DX = d1(f, h);
+        S DX = dD(f, d);
         vc = vc - g.rhoD[ks * n + c0] * (DX + (g.X[ks * n + c0] - g.Y[ks * n + c0]) * Dp / g.p[c0]);
         for (int s = -4; s <= 4; ++s) f[s + 4] = g.Y[ks * n + pt(d, s)];
-        DY[d * ns + ks] = d1(f, h);
+        DY[d * ns + ks] = dD(f, d);
         for (int s = -4; s <= 4; ++s) {
           long c = pt(d, s);
           f[s + 4] = g.h[ks * n + c] * g.Y[ks * n + c];
         }
-        DhY[d * ns + ks] = d1(f, h);
+        DhY[d * ns + ks] = dD(f, d);
       }
       Vc[d] = vc;
     }
@@ -598,6 +729,39 @@ double oracle_narrow_point(const double *a9, const double *u9, double dx, double
   double M[8][8];
   narrow8(m47, m48, M);
   return narrow(a9, u9, dx, M);
+}
+
+// The boundary stencils on a line of n >= 8 points with physical boundaries
+// at both ends (kind 0 advection, 1 diffusion for the first derivative).
+void oracle_d1_line(int n, const double *f, double dx, int kind, double *out) {
+  for (int i = 0; i < n; ++i) {
+    double s[9];
+    for (int o = -4; o <= 4; ++o) s[o + 4] = f[std::min(std::max(i + o, 0), n - 1)];
+    const int b = std::min(i, n - 1 - i), high = (n - 1 - i) < i;
+    out[i] = d1_bnd(s, dx, b, high, kind ? DIFFUSION : ADVECTION);
+  }
+}
+
+void oracle_narrow_line(int n, const double *a, const double *u, double dx, double m47, double m48,
+                        double *out) {
+  double M[8][8];
+  narrow8(m47, m48, M);
+  for (int i = 0; i < n; ++i) {
+    double as[9], us[9];
+    for (int o = -4; o <= 4; ++o) {
+      const int c = std::min(std::max(i + o, 0), n - 1);
+      as[o + 4] = a[c];
+      us[o + 4] = u[c];
+    }
+    const int b = std::min(i, n - 1 - i), high = (n - 1 - i) < i;
+    out[i] = narrow_bnd(as, us, dx, b, high, M);
+  }
+}
+
+void oracle_narrow4_matrix(double *M) {
+  double T[4][4];
+  narrow4(T);
+  std::memcpy(M, T, sizeof(T));
 }
 
 void oracle_d1_periodic(int n, const double *f, double dx, double *out) {

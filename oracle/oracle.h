@@ -35,6 +35,10 @@ typedef struct {
   /* second derivatives (a u_x)_x: 0 the narrow stencil (eq. H), 1 the wide
      stencil D(a D u) of two eighth-order first derivatives (Section 2.2) */
   int wide_stencil;
+  /* bit d set: direction d has physical (non-periodic) boundaries at both
+     ends, with the reduced-order boundary stencils of Section 2.5 (needs at
+     least 8 interior cells along d and the narrow stencil) */
+  int nonperiodic;
 } omech;
 
 enum { ORC_HYP = 1, ORC_DIFF = 2, ORC_REACT = 4 };
@@ -48,6 +52,16 @@ void oracle_narrow6_matrix(double m36, double *M);
 /* Operators at the centre of a 9-sample line f[0..8] (index 4 = centre). */
 double oracle_d1_point(const double *f9, double dx);
 double oracle_narrow_point(const double *a9, const double *u9, double dx, double m47, double m48);
+
+/* A line of n >= 8 points with physical boundaries at both ends: the first
+ * derivative (kind 0 advection, 1 diffusion) and d/dx(a du/dx) with the
+ * boundary stencils of Section 2.5 (eighth-order stencils from the fifth
+ * point on). */
+void oracle_d1_line(int n, const double *f, double dx, int kind, double *out);
+void oracle_narrow_line(int n, const double *a, const double *u, double dx, double m47, double m48,
+                        double *out);
+/* 4x4 matrix of the fourth-order narrow stencil, entry [(m+1)*4 + (n+1)], m,n in -1..2. */
+void oracle_narrow4_matrix(double *M);
 
 /* Periodic 1D and 2D operators. */
 void oracle_d1_periodic(int n, const double *f, double dx, double *out);
