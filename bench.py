@@ -106,7 +106,8 @@ def cpu_baseline(workload, mech, n_cells_full):
     from oracle import sdc as osdc
     from synth.workloads import WORKLOADS, make_primitives, time_step
     wl = WORKLOADS[workload]
-    om = oracle.Mechanism(mech, ref_species=wl.get("ref_species", -1), wide=wl.get("wide", False))
+    om = oracle.Mechanism(mech, ref_species=wl.get("ref_species", -1), wide=wl.get("wide", False),
+                          nonperiodic=wl.get("nonperiodic", 0))
     # about 10-30 s of host work: a 64^3 box with 9 species, 48^3 with 21,
     # 24^3 for the implicit-chemistry scheme (its Newton solves take the
     # oracle's tangent products)
@@ -410,7 +411,7 @@ def run_box(args, workload, steps, warmup, with_baseline):
     ctx.set_residual_exit(wl.get("residual_ratio", 0.0))
     ctx.set_wide_stencil(wl.get("wide", False))
     prim = make_primitives(workload, mech)
-    bx = N.box(nx, ny, nz, dx)
+    bx = N.box(nx, ny, nz, dx, nonperiodic=wl.get("nonperiodic", 0))
     U = torch.zeros(N.ghosted_shape(5 + ns, nz, ny, nx), dtype=torch.float64, device="cuda")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     ctx.prim_to_cons(bx, dev(prim["p"]), dev(prim["T"]), dev(prim["Y"]), dev(prim["u"]), U)
@@ -492,7 +493,10 @@ def run_box(args, workload, steps, warmup, with_baseline):
                    "second_derivatives": "wide stencil D(a D u)" if wl.get("wide") else "narrow stencil",
                    "species_diffusion":
                    ("reference species %d" % wl["ref_species"]) if wl.get("ref_species", -1) >= 0
-                   else "correction velocity"},
+                   else "correction velocity",
+                   "boundaries": "physical along " + "".join(a for d, a in enumerate("xyz")
+                                                             if (wl.get("nonperiodic", 0) >> d) & 1)
+                   if wl.get("nonperiodic", 0) else "periodic"},
         "mcell_ad_evals_per_s": ncell * n_ad / el / 1e6,
         ("mcell_implicit_chem_solves_per_s" if mode2 else "mcell_r_evals_per_s"): ncell * n_r / el / 1e6,
         "kernels_ms": {k: round(v[0], 4) for k, v in kern.items()},

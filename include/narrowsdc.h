@@ -52,10 +52,24 @@ enum { RHS_HYP = 1, RHS_DIFF = 2, RHS_REACT = 4, RHS_AD = 3, RHS_ALL = 7 };
 
 typedef struct sdc_context sdc_context;
 
+/* One box.  nonperiodic: bit d (1 x, 2 y, 4 z) set for physical boundaries
+ * at both ends of direction d instead of periodic wrap-around (Section 2.5):
+ * the stencils along that direction drop in order near the boundary (the
+ * fourth and third cells from it: sixth- and fourth-order centred first
+ * derivatives and narrow stencils; the next cell: second-order centred
+ * diffusion and third-order advection biased away from the boundary; the
+ * boundary cell: one-sided second-order diffusion and third-order
+ * advection), using interior cells only; the ghost layers along d are
+ * filled with copies of the boundary cells and never read by a stencil.
+ * Needs at least 8 cells along d and the narrow stencil; the adjoint covers
+ * periodic boxes only (SDC_EINVAL).  The paper's characteristic boundary
+ * conditions are not applied: the boundary cells evolve by the one-sided
+ * stencils alone. */
 typedef struct {
   int nx, ny, nz;     /* interior cells, each >= 1 */
   int ng;             /* ghost layers: must be 4 */
   double dx, dy, dz;  /* grid spacing, m */
+  int nonperiodic;    /* 0: periodic in every direction */
 } box_desc;
 
 /* Chemical mechanism and transport model (host pointers, deep-copied by

@@ -121,6 +121,10 @@ struct Plan {
   TileShape tsI{}, tsS{};
   TileShape tsZ{};             // tile of the z stencil pass
   int nZ = 0;                  // its work items
+  // the boundary layers (4 cells deep) of the directions with physical
+  // boundaries: work items of the boundary variant of the stencil passes
+  int nB[3] = {0, 0, 0};
+  TileShape tsB[3] = {{4, 8, 8}, {16, 4, 4}, {16, 4, 4}};
   int cap = 0;                 // workgroups per launch (0: one per work item)
   double **d_Utab = nullptr;
   std::vector<double *> Uptrs;
@@ -167,8 +171,8 @@ std::string plan_key(int nbox, const box_desc *b, double *const *U, TileShape tI
   snprintf(buf, sizeof buf, "n%d|%d,%d,%d|%d,%d,%d|", nbox, tI.tx, tI.ty, tI.tz, tS.tx, tS.ty, tS.tz);
   k += buf;
   for (int i = 0; i < nbox; ++i) {
-    snprintf(buf, sizeof buf, "%d,%d,%d,%.17g,%.17g,%.17g,%p;", b[i].nx, b[i].ny, b[i].nz, b[i].dx,
-             b[i].dy, b[i].dz, U ? (void *)U[i] : nullptr);
+    snprintf(buf, sizeof buf, "%d,%d,%d,%.17g,%.17g,%.17g,np%d,%p;", b[i].nx, b[i].ny, b[i].nz, b[i].dx,
+             b[i].dy, b[i].dz, b[i].nonperiodic, U ? (void *)U[i] : nullptr);
     k += buf;
   }
   return k;
@@ -339,6 +343,13 @@ int check_box(sdc_context *c, const box_desc *b) {
   if (b->nx < 1 || b->ny < 1 || b->nz < 1) return fail(c, SDC_EINVAL, "box extents must be >= 1");
   if (b->ng != NSDC_NG) return fail(c, SDC_EINVAL, "ghost layers must be 4");
   if (!(b->dx > 0) || !(b->dy > 0) || !(b->dz > 0)) return fail(c, SDC_EINVAL, "grid spacing must be > 0");
+  if (b->nonperiodic & ~7) return fail(c, SDC_EINVAL, "nonperiodic takes bits 1 (x), 2 (y), 4 (z)");
+  const int dims[3] = {b->nx, b->ny, b->nz};
+  for (int d = 0; d < 3; ++d)
+    if (((b->nonperiodic >> d) & 1) && dims[d] < 8)
+      return fail(c, SDC_EINVAL, "a direction with physical boundaries needs at least 8 cells");
+  if (b->nonperiodic && c->wide)
+    return fail(c, SDC_EINVAL, "physical boundaries need the narrow stencil (set_wide_stencil(0))");
   const long long s = (long long)(b->nx + 8) * (b->ny + 8) * (b->nz + 8);
   if (s >= (1LL << 28)) return fail(c, SDC_EINVAL, "box too large (stored cells must be < 2^28)");
   return SDC_OK;
@@ -349,7 +360,7 @@ std::string box_signature(int nbox, const box_desc *b) {
   std::string k;
   char buf[64];
   for (int i = 0; i < nbox; ++i) {
-    snprintf(buf, sizeof buf, "%d,%d,%d;", b[i].nx, b[i].ny, b[i].nz);
+    snprintf(buf, sizeof buf, "%d,%d,%d,%d;", b[i].nx, b[i].ny, b[i].nz, b[i].nonperiodic);
     k += buf;
   }
   return k;
@@ -395,11 +406,12 @@ void plan_layout(const sdc_context *c, Plan *p, std::vector<BoxDev> &hb, std::ve
   p->tsZ = tZ;
   p->totS = p->totI = 0;
   hb.assign(nbox, BoxDev{});
-  std::vector<Item> iI, iS, iG, iY, iZ;
+  std::vector<Item> iI, iS, iG, iY, iZ, iB[3];
   for (int b = 0; b < nbox; ++b) {
     BoxDev &d = hb[b];
     d.nx = bx[b].nx; d.ny = bx[b].ny; d.nz = bx[b].nz;
     d.sx = d.nx + 2 * NSDC_NG; d.sy = d.ny + 2 * NSDC_NG; d.sz = d.nz + 2 * NSDC_NG;
+    d.np = bx[b].nonperiodic;
     d.offS = p->totS;
     d.offI = p->totI;
     const double h[3] = {bx[b].dx, bx[b].dy, bx[b].dz};
@@ -425,14 +437,31 @@ void plan_layout(const sdc_context *c, Plan *p, std::vector<BoxDev> &hb, std::ve
         for (int x = 0; x < d.sx; x += tS.tx) iS.push_back(Item{b, x, y, z});
     const long long ng = (long long)d.sx * d.sy * d.sz - (long long)d.nx * d.ny * d.nz;
     for (long long g = 0; g < ng; g += 256) iG.push_back(Item{b, (int)g, 0, 0});
+    // boundary layers: tiles 4 cells deep at both ends of each direction
+    // with physical boundaries (at least 8 cells, so the two are disjoint)
+    const int n3[3] = {d.nx, d.ny, d.nz};
+    for (int dd = 0; dd < 3; ++dd) {
+      if (!((d.np >> dd) & 1)) continue;
+      const TileShape t = p->tsB[dd];
+      const int ext[3] = {t.tx, t.ty, t.tz};
+      for (int side = 0; side < 2; ++side) {
+        int lo[3] = {0, 0, 0}, hi[3] = {d.nx, d.ny, d.nz};
+        lo[dd] = side ? n3[dd] - 4 : 0;
+        hi[dd] = lo[dd] + 4;
+        for (int z = lo[2]; z < hi[2]; z += ext[2])
+          for (int y = lo[1]; y < hi[1]; y += ext[1])
+            for (int x = lo[0]; x < hi[0]; x += ext[0]) iB[dd].push_back(Item{b, x, y, z});
+      }
+    }
   }
   p->nI = (int)iI.size();
   p->nS = (int)iS.size();
   p->nG = (int)iG.size();
   p->nZ = (int)iZ.size();
+  for (int dd = 0; dd < 3; ++dd) p->nB[dd] = (int)iB[dd].size();
   const long long capE = c->grid_cap > 0 ? c->grid_cap : (p->cap > 0 ? p->cap : (1LL << 30));
   all.clear();
-  for (const std::vector<Item> *v : {&iI, &iS, &iG, &iY, &iZ}) {
+  for (const std::vector<Item> *v : {&iI, &iS, &iG, &iY, &iZ, &iB[0], &iB[1], &iB[2]}) {
     const std::vector<Item> o = xcd_order(*v, std::min<long long>((long long)v->size(), capE));
     all.insert(all.end(), o.begin(), o.end());
   }
@@ -490,6 +519,13 @@ LaunchCtx make_lc_at(sdc_context *c, const Plan *p, BoxDev *d_boxes, Item *d_ite
   l.itemsD[2] = l.itemsD[1] + p->nI;
   l.nD[0] = l.nD[1] = p->nI;
   l.nD[2] = p->nZ;
+  const Item *bi = l.itemsD[2] + p->nZ;
+  for (int d = 0; d < 3; ++d) {
+    l.itemsB[d] = bi;
+    l.nB[d] = p->nB[d];
+    l.tsB[d] = p->tsB[d];
+    bi += p->nB[d];
+  }
   l.tsD[0] = l.tsD[1] = p->tsI;
   l.tsD[2] = p->tsZ;
   l.nI = p->nI;
@@ -970,6 +1006,81 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
 
 }  // namespace
 
+// Stencils near a physical boundary (Section 2.5) as weights on the nine
+// samples centred on a cell b = 0..3 cells from the boundary: first
+// derivatives of the advective terms (sixth- and fourth-order centred for
+// b = 3, 2; third order biased away from the boundary for b = 1; one-sided
+// third order for b = 0) and of the diffusive terms (the same for b = 3, 2;
+// second-order centred for b = 1, one-sided second order for b = 0), and the
+// second-derivative pairs as the matrix K of (a u_x)_x h^2 = sum a_o K_oc u_c:
+// the sixth-order narrow stencil (Section 2.2, m36 = 281/3600) for b = 3, the
+// fourth-order member of the same family for b = 2 (corner entries zero,
+// m33 = 1/72), faces (a_i + a_{i+1})(u_{i+1} - u_i)/2 for b = 1, and
+// a_0 u'' + a' u' with one-sided second-order differences for b = 0.  The
+// boundary above is the mirror image: first-derivative weights reversed and
+// negated, K reversed in both indices.
+static void boundary_stencils(DevMech &d) {
+  std::memset(d.bwA, 0, sizeof d.bwA);
+  std::memset(d.bwD, 0, sizeof d.bwD);
+  std::memset(d.bK, 0, sizeof d.bK);
+  // sample index o = 4 + offset
+  auto central = [&](double w[9], const double *c, int n) {
+    for (int s = 1; s <= n; ++s) {
+      w[4 + s] = c[s - 1];
+      w[4 - s] = -c[s - 1];
+    }
+  };
+  const double c6[3] = {3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0}, c4[2] = {2.0 / 3.0, -1.0 / 12.0};
+  central(d.bwA[3], c6, 3);
+  central(d.bwD[3], c6, 3);
+  central(d.bwA[2], c4, 2);
+  central(d.bwD[2], c4, 2);
+  d.bwA[1][3] = -2.0 / 6.0; d.bwA[1][4] = -3.0 / 6.0; d.bwA[1][5] = 6.0 / 6.0; d.bwA[1][6] = -1.0 / 6.0;
+  d.bwD[1][3] = -0.5; d.bwD[1][5] = 0.5;
+  d.bwA[0][4] = -11.0 / 6.0; d.bwA[0][5] = 18.0 / 6.0; d.bwA[0][6] = -9.0 / 6.0; d.bwA[0][7] = 2.0 / 6.0;
+  d.bwD[0][4] = -1.5; d.bwD[0][5] = 2.0; d.bwD[0][6] = -0.5;
+  // face-sum stencils: H_{i+1/2} = sum_{m,n} a_{i+m} M_{mn} u_{i+n}, K += the
+  // face above minus the face below
+  auto faces = [&](double K[9][9], const double *M, int lo, int w) {
+    for (int m = 0; m < w; ++m)
+      for (int n = 0; n < w; ++n) {
+        const double v = M[m * w + n];
+        K[4 + lo + m][4 + lo + n] += v;
+        K[3 + lo + m][3 + lo + n] -= v;
+      }
+  };
+  const double m36 = 281.0 / 3600.0;
+  const double q11 = -11.0 / 180 + m36, q12 = 1.0 / 9 - 2 * m36, q13 = -1.0 / 18 + m36, q14 = 1.0 / 180;
+  const double q21 = 7.0 / 60 - 3 * m36, q22 = -1.0 / 120 + 5 * m36, q23 = -17.0 / 90 - 2 * m36;
+  const double q24 = 5.0 / 72 + m36, q25 = 1.0 / 90 - m36, q31 = -1.0 / 15 + 3 * m36;
+  const double q32 = -11.0 / 60 - 3 * m36, q33 = -101.0 / 360, q34 = 137.0 / 180 - 2 * m36;
+  const double q35 = -83.0 / 360 + m36;
+  const double M6[36] = {q11,  q12,  q13,  q14,  0,    0,    q21,  q22,  q23,  q24,  q25,  0,
+                         q31,  q32,  q33,  q34,  q35,  m36,  -m36, -q35, -q34, -q33, -q32, -q31,
+                         0,    -q25, -q24, -q23, -q22, -q21, 0,    0,    -q14, -q13, -q12, -q11};
+  faces(d.bK[3], M6, -2, 6);
+  const double e = 1.0 / 72.0;
+  const double M4[16] = {-e,          2 * e + 1.0 / 12, -e - 1.0 / 12,  0,
+                         2 * e + 1.0 / 12, -3 * e - 0.75,  2.0 / 3,    e,
+                         -e,          -2.0 / 3,      3 * e + 0.75, -2 * e - 1.0 / 12,
+                         0,           e + 1.0 / 12,  -2 * e - 1.0 / 12, e};
+  faces(d.bK[2], M4, -1, 4);
+  const double M2[4] = {-0.5, 0.5, -0.5, 0.5};
+  faces(d.bK[1], M2, 0, 2);
+  const double c2[9] = {0, 0, 0, 0, 2.0, -5.0, 4.0, -1.0, 0};
+  const double c1[9] = {0, 0, 0, 0, -1.5, 2.0, -0.5, 0, 0};
+  for (int cc = 0; cc < 9; ++cc) {
+    d.bK[0][4][cc] += c2[cc];
+    for (int o = 0; o < 9; ++o) d.bK[0][o][cc] += c1[o] * c1[cc];
+  }
+  for (int b = 0; b < 4; ++b)
+    for (int o = 0; o < 9; ++o) {
+      d.bwA[4 + b][o] = -d.bwA[b][8 - o];
+      d.bwD[4 + b][o] = -d.bwD[b][8 - o];
+      for (int cc = 0; cc < 9; ++cc) d.bK[4 + b][o][cc] = d.bK[b][8 - o][8 - cc];
+    }
+}
+
 // ================================================================ C ABI
 extern "C" {
 
@@ -1111,6 +1222,7 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
   for (int o = 0; o < 9; ++o)
     for (int col = 0; col < 9; ++col)
       d.B[o][col] = ((o >= 1 && col >= 1) ? d.M[o - 1][col - 1] : 0.0) - ((o <= 7 && col <= 7) ? d.M[o][col] : 0.0);
+  boundary_stencils(d);
   // a new mechanism starts in the correction-velocity form
   d.ref = -1;
   HIPCHECK(c, hipSetDevice(c->device));
@@ -1609,6 +1721,7 @@ int check_vjp_args(sdc_context *c, const box_desc *box) {
   if (c->wide) return fail(c, SDC_EINVAL, "the adjoint covers the narrow stencil only");
   int rc = check_box(c, box);
   if (rc) return rc;
+  if (box->nonperiodic) return fail(c, SDC_EINVAL, "the adjoint covers periodic boxes only");
   const TileShape t = c->forceI;
   if (t.tx && (t.tx * t.ty * t.tz) % 64) return fail(c, SDC_EINVAL, "interior tile must be a multiple of 64 threads");
   return SDC_OK;
@@ -1818,7 +1931,7 @@ int sdc_vjp_workspace_size(const sdc_context *c, const box_desc *box, const sdc_
   if (!c || !bytes || nsteps < 1) return SDC_EINVAL;
   if (!c->has_mech) return SDC_ENOMECH;
   sdc_context *cc = const_cast<sdc_context *>(c);
-  if (check_box(cc, box) || check_scheme(cc, scheme) || scheme->n_fine != 0) return SDC_EINVAL;
+  if (check_box(cc, box) || check_scheme(cc, scheme) || scheme->n_fine != 0 || box->nonperiodic) return SDC_EINVAL;
   Plan *pl;
   if (get_plan(cc, 1, box, nullptr, &pl)) return SDC_EHIP;
   *bytes = sdc_vjp_layout(pl, c->ops->ns, c->h_mech.nr, grid_cap_of(c, pl), scheme, nsteps).total * sizeof(double);

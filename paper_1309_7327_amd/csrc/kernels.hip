@@ -113,9 +113,12 @@ __global__ __launch_bounds__(256) void k_ghost(const BoxDev *__restrict__ boxes,
       const int xx = (int)(r % (2 * NSDC_NG));
       x = xx < NSDC_NG ? xx : b.nx + xx;
     }
-    const int xs = ((x - NSDC_NG) % b.nx + b.nx) % b.nx + NSDC_NG;
-    const int ys = ((y - NSDC_NG) % b.ny + b.ny) % b.ny + NSDC_NG;
-    const int zs = ((z - NSDC_NG) % b.nz + b.nz) % b.nz + NSDC_NG;
+    // the periodic image, or along a direction with physical boundaries the
+    // nearest boundary cell (a finite state no stencil reads)
+    auto src_of = [&](int c, int n, int d) {
+      return ((b.np >> d) & 1) ? min(max(c - NSDC_NG, 0), n - 1) + NSDC_NG : ((c - NSDC_NG) % n + n) % n + NSDC_NG;
+    };
+    const int xs = src_of(x, b.nx, 0), ys = src_of(y, b.ny, 1), zs = src_of(z, b.nz, 2);
     const long long nS = (long long)b.sx * b.sy * b.sz;
     const long long dst = ((long long)z * b.sy + y) * b.sx + x;
     const long long src = ((long long)zs * b.sy + ys) * b.sx + xs;
@@ -214,7 +217,7 @@ template <int NS>
 __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
                                                TileShape ts, const double *__restrict__ Pbase,
-                                               double *__restrict__ Gbase) {
+                                               double *__restrict__ Gbase, const DevMech *__restrict__ m) {
   using L = Layout<NS>;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
@@ -232,13 +235,27 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       if (c[j] < NSDC_NG || c[j] >= n[j] + NSDC_NG) continue;
+      // within 4 cells of a physical boundary along j: its diffusive
+      // first-derivative stencil (Section 2.5)
+      const int cj = c[j] - NSDC_NG, bj = min(cj, n[j] - 1 - cj);
+      const bool bnd = ((b.np >> j) & 1) && bj < 4;
+      const double *wb = m->bwD[bnd ? bj + (n[j] - 1 - cj < cj ? 4 : 0) : 0];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const double *f = P + (L::PU + i) * nS + s;
         double v[9];
 #pragma unroll
         for (int o = 0; o < 9; ++o) v[o] = f[(o - 4) * st[j]];
-        G[(3 * j + i) * nS + s] = d1(v, b.idx[j]);
+        double g;
+        if (bnd) {
+          g = 0.0;
+#pragma unroll
+          for (int o = 0; o < 9; ++o) g += wb[o] * v[o];
+          g *= b.idx[j];
+        } else {
+          g = d1(v, b.idx[j]);
+        }
+        G[(3 * j + i) * nS + s] = g;
       }
     }
   }
@@ -254,8 +271,13 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
 // parts: bit 1 the convective terms, bit 2 the diffusive terms, bit 8 store
 // the pass's sums into F instead of adding them (the first pass of an
 // evaluation that nothing wrote to before).
-template <int NS, int D, bool FIXED, bool REF, bool WIDE>
-__global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
+// Physical boundaries along D (Section 2.5): the plain instances skip the
+// cells within 4 of them; the BND instance runs on exactly those cells (its
+// own work list) with the boundary stencils of the mechanism tables: first
+// derivatives of the advective and of the diffusive terms, and the matrix K
+// of the second-derivative pairs in place of the face-difference matrix B.
+template <int NS, int D, bool FIXED, bool REF, bool WIDE, bool BND>
+__global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
                                              TileShape ts, FRef Uref,
                                              const double *__restrict__ Pbase,
@@ -278,6 +300,15 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
     int x, y, z;
     tile_cell(w, ts, x, y, z);
     if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+    // cells within 4 of a physical boundary along D belong to the BND
+    // instance; vb = its stencil variant (distance + 4 for the upper side)
+    const int cD = D == 0 ? x : (D == 1 ? y : z), nDd = D == 0 ? b.nx : (D == 1 ? b.ny : b.nz);
+    int vb = 0;
+    if constexpr (BND) {
+      vb = min(cD, nDd - 1 - cD) + (nDd - 1 - cD < cD ? 4 : 0);
+    } else {
+      if (((b.np >> D) & 1) && (cD < 4 || cD >= nDd - 4)) continue;
+    }
     // per-lane cell indices are 32-bit; everything uniform (field bases,
     // stencil offsets) goes into the 64-bit base of each load
     const long long nS = (long long)b.sx * b.sy * b.sz;
@@ -290,6 +321,47 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
     const double *G = Gbase + b.offS * 9;
     double *F = Fout.get(w.box, b.offI * NU);
     const double idx = b.idx[D], idx2 = b.idx2[D];
+    // first derivatives of the advective (DA) and diffusive (DD) terms, of
+    // a pointwise product (DAP, DDP), and v = B u (BV) for the pairs
+    const double *wA = m->bwA[vb], *wD = m->bwD[vb];
+    auto dotw = [&](const double *w, const double *f) {
+      double r = 0.0;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) r += w[o] * f[o];
+      return r * idx;
+    };
+    auto dotwp = [&](const double *w, const double *f, const double *g) {
+      double r = 0.0;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) r += w[o] * (f[o] * g[o]);
+      return r * idx;
+    };
+    auto DA = [&](const double *f) -> double {
+      if constexpr (BND) return dotw(wA, f); else return d1(f, idx);
+    };
+    auto DD = [&](const double *f) -> double {
+      if constexpr (BND) return dotw(wD, f); else return d1(f, idx);
+    };
+    auto DAP = [&](const double *f, const double *g) -> double {
+      if constexpr (BND) return dotwp(wA, f, g); else return d1p(f, g, idx);
+    };
+    auto DDP = [&](const double *f, const double *g) -> double {
+      if constexpr (BND) return dotwp(wD, f, g); else return d1p(f, g, idx);
+    };
+    auto BV = [&](const double *u, double *v) {
+      if constexpr (BND) {
+        const double(*K)[9] = m->bK[vb];
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+          double a = 0.0;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) a += K[o][c] * u[c];
+          v[o] = a;
+        }
+      } else {
+        bvec<FIXED>(m, u, v);
+      }
+    };
     double acc[ACC_LDS ? 5 : NU];
 #pragma unroll
     for (int q = 0; q < (ACC_LDS ? 5 : NU); ++q) acc[q] = 0.0;
@@ -356,20 +428,20 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
 #pragma unroll
       for (int ic = 0; ic < 3; ++ic) {
         line(U + (1 + ic) * nS, f);
-        if (ic == D) acc[0] -= d1(f, idx);
+        if (ic == D) acc[0] -= DA(f);
 #pragma unroll
         for (int o = 0; o < 9; ++o) f[o] = f[o] * ud[o] + (ic == D ? pp[o] : 0.0);
-        acc[1 + ic] -= d1(f, idx);
+        acc[1 + ic] -= DA(f);
       }
       line(U + 4 * nS, f);
 #pragma unroll
       for (int o = 0; o < 9; ++o) f[o] += pp[o];
-      acc[4] -= d1p(f, ud, idx);
+      acc[4] -= DAP(f, ud);
       if (hyp_species_apart) {
 #pragma unroll 1
         for (int k = 0; k < NS; ++k) {
           line(U + (5 + k) * nS, f);
-          spc(k) -= d1p(f, ud, idx);
+          spc(k) -= DAP(f, ud);
         }
       }
     }
@@ -401,7 +473,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
               g[o] = lam2 * mu[o] * (g[o] + v[o]);
               fe[o] += u9[o] * g[o];
             }
-            acc[1 + D] += d1(g, idx);
+            acc[1 + D] += DD(g);
             double w2[17];
 #pragma unroll
             for (int o = 0; o < 17; ++o) w2[o] = 0.5 * w[o] * w[o];
@@ -414,11 +486,11 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
               g[o] *= mu[o];
               fe[o] += u9[o] * g[o];
             }
-            acc[1 + ic] += d1(g, idx);
+            acc[1 + ic] += DD(g);
           }
         }
         wvec(ke, v);
-        acc[4] += dot9(mu, v) * idx2 + d1(fe, idx);
+        acc[4] += dot9(mu, v) * idx2 + DD(fe);
         line17(P + L::PT * nS, w);
         wvec(w, v);
         line(P + L::PLAM * nS, g);
@@ -438,7 +510,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
           }
           // viscous stress, second-derivative part: L_D(a, u_ic),
           // a = (4/3 mu + xi) along D, mu across
-          bvec<FIXED>(m, u9, v);
+          BV(u9, v);
           acc[1 + ic] += (ic == D ? 4.0 / 3.0 + bulk : 1.0) * dot9(mu, v) * idx2;
 #pragma unroll
           for (int o = 0; o < 9; ++o) ke[o] += 0.5 * u9[o] * u9[o];
@@ -451,11 +523,11 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
               g[o] = lam2 * mu[o] * (g[o] + v[o]);
               fe[o] += u9[o] * g[o];
             }
-            acc[1 + D] += d1(g, idx);
+            acc[1 + D] += DD(g);
             // viscous work L_D(mu/3 + xi, u_D^2 / 2)
 #pragma unroll
             for (int o = 0; o < 9; ++o) g[o] = 0.5 * u9[o] * u9[o];
-            bvec<FIXED>(m, g, v);
+            BV(g, v);
             acc[4] += (1.0 / 3.0 + bulk) * dot9(mu, v) * idx2;
           } else {
             // D_D(mu D_ic u_D) and its viscous-work part mu u_ic D_ic u_D
@@ -465,15 +537,15 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
               g[o] *= mu[o];
               fe[o] += u9[o] * g[o];
             }
-            acc[1 + ic] += d1(g, idx);
+            acc[1 + ic] += DD(g);
           }
         }
         // viscous work L_D(mu, |u|^2/2) and the first-derivative part
-        bvec<FIXED>(m, ke, v);
-        acc[4] += dot9(mu, v) * idx2 + d1(fe, idx);
+        BV(ke, v);
+        acc[4] += dot9(mu, v) * idx2 + DD(fe);
         // heat conduction L_D(lambda, T)
         line(P + L::PT * nS, u9);
-        bvec<FIXED>(m, u9, v);
+        BV(u9, v);
         line(P + L::PLAM * nS, g);
         acc[4] += dot9(g, v) * idx2;
       }
@@ -487,7 +559,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
           line17(P + L::PP * nS, w);
           wvec(w, v);
         } else {
-          bvec<FIXED>(m, pp, v);
+          BV(pp, v);
         }
         // X_k's centre samples into u9 and its pair vector into v
         auto xpair = [&](const double *f, double *u9o, double *vo) {
@@ -499,12 +571,12 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
             wvec(w, vo);
           } else {
             line(f, u9o);
-            bvec<FIXED>(m, u9o, vo);
+            BV(u9o, vo);
           }
         };
 #pragma unroll
         for (int o = 0; o < 9; ++o) wp[o] = rd[o] * v[o] / pp[o];
-        const double Dpp = d1(pp, idx) / pp[4];
+        const double Dpp = DD(pp) / pp[4];
         const double rd4 = rd[4];
         double divVc = 0.0, Vc = 0.0;
         if constexpr (REF) {
@@ -517,7 +589,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
           for (int k = 0; k < NS; ++k) {
             if (HYP_IN_SPECIES && (parts & 1)) {
               line(U + (5 + k) * nS, u9);
-              spc(k) -= d1p(u9, ud, idx);
+              spc(k) -= DAP(u9, ud);
             }
             if (k == ref) continue;
             const double iLe = m->invLe[k];
@@ -565,7 +637,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
             double y9[9];
             if (HYP_IN_SPECIES && (parts & 1)) {
               line(U + (5 + k) * nS, y9);
-              spc(k) -= d1p(y9, ud, idx);
+              spc(k) -= DAP(y9, ud);
             }
             if constexpr (WIDE) {
               xpair(P + (L::PX + k) * nS, u9, v);
@@ -576,9 +648,9 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
               line(P + (L::PX + k) * nS, u9);
               line(P + (L::PY + k) * nS, y9);
               line(P + (L::PH + k) * nS, g);
-              bvec<FIXED>(m, u9, v);
+              BV(u9, v);
             }
-            const double DX = d1(u9, idx);
+            const double DX = DD(u9);
             const double dXY4 = u9[4] - y9[4];
 #pragma unroll
             for (int o = 0; o < 9; ++o) u9[o] -= y9[o];
@@ -596,9 +668,9 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
             acc[4] += iLe * (LhX + Lpe) * idx2;
             Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
             ysh[k * 256] = y9[4];
-            ysh[(NS + k) * 256] = d1(y9, idx);
+            ysh[(NS + k) * 256] = DD(y9);
             ShY += g[4] * y9[4];
-            SDhY += d1p(g, y9, idx);
+            SDhY += DDP(g, y9);
           }
           // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart
 #pragma unroll
@@ -610,10 +682,10 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
             const double iLe = m->invLe[k];
             if (HYP_IN_SPECIES && (parts & 1)) {
               line(U + (5 + k) * nS, u9);
-              spc(k) -= d1p(u9, ud, idx);
+              spc(k) -= DAP(u9, ud);
             }
             xpair(P + (L::PX + k) * nS, u9, v);
-            const double DX = d1(u9, idx);
+            const double DX = DD(u9);
             line(P + (L::PY + k) * nS, g);
             const double dXY4 = u9[4] - g[4];
 #pragma unroll
@@ -638,8 +710,8 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE ? 3 : 2) void k_dir
           for (int k = 0; k < NS; ++k) {
             line(P + (L::PY + k) * nS, u9);
             line(P + (L::PH + k) * nS, g);
-            const double DY = d1(u9, idx);
-            const double DhY = d1p(g, u9, idx);
+            const double DY = DD(u9);
+            const double DhY = DDP(g, u9);
             spc(k) += u9[4] * divVc + Vc * DY;
             acc[4] += g[4] * u9[4] * divVc + Vc * DhY;
           }
@@ -1251,30 +1323,35 @@ namespace nsdc {
 // dw/dy from mass action (dq_j/dc_m) and the Arrhenius and equilibrium
 // temperature dependence (dq_j/dT) with the temperature following the
 // species at fixed internal energy: dT/dy_m = -e_m(T) / (rho c_v).  The
-// per-cell arrays live in the lane's workspace slot sl (entry i at sl[i st]):
-//   A [NS][NS] | y | b | G | c [NS+1] | g [NS+1] | h/RT [NS+1] | aT [NS+1] | w [NS+1]
-// (index NS of the last five is the dummy species of absent molecules).
+// runtime-indexed per-cell arrays live in a slot sl (entry i at sl[i st]):
+// in LDS (st = 64, one wave per workgroup, up to 9 species) or in the lane's
+// slot of a workspace region (st = the launch's lanes):
+//   A [NS][NS] | G [NS] | c [NS+1] | g [NS+1] | h/RT [NS+1] | aT [NS+1] | w [NS+1]
+// (index NS of the last five is the dummy species of absent molecules); y
+// and b stay in registers.
 template <int NS>
 struct Mr2Slot {
   double *p;
   long long st;
-  static constexpr int A = 0, Y = NS * NS, B = Y + NS, G = B + NS, C = G + NS, GR = C + NS + 1,
-                       HR = GR + NS + 1, AT = HR + NS + 1, W = AT + NS + 1;
+  static constexpr int A = 0, G = NS * NS, C = G + NS, GR = C + NS + 1, HR = GR + NS + 1, AT = HR + NS + 1,
+                       W = AT + NS + 1;
   __device__ double &operator()(int i) const { return p[i * st]; }
   __device__ double &a(int r, int c) const { return p[(r * NS + c) * st]; }
 };
 static_assert(Mr2Slot<21>::W + 22 == NSDC_MR2_SLOT(21), "mode-2 slot layout");
 
 template <int NS>
-__device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<NS> &sl, double rho, double T,
-                                   double cv, double h) {
+__device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<NS> &sl, const double *y,
+                                   double rho, double T, double cv, double h) {
   const double lnT = log(T), invT = 1.0 / T;
+#pragma unroll
   for (int k = 0; k < NS; ++k) {
-    sl(sl.C + k) = sl(sl.Y + k) * m->invW[k];
+    sl(sl.C + k) = y[k] * m->invW[k];
     sl(sl.GR + k) = g_RT(m, k, T, invT, lnT);
     sl(sl.HR + k) = h_RT(m, k, T, invT);
     sl(sl.AT + k) = 0.0;
     sl(sl.W + k) = 0.0;
+#pragma unroll
     for (int c = 0; c < NS; ++c) sl.a(k, c) = 0.0;
   }
   sl(sl.C + NS) = 1.0;
@@ -1300,24 +1377,28 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
     const double dqdT = fwd * dlkf - rev * dlkr;
     // dq/dc of the four slots (a species twice gets both terms)
     const double dq[4] = {kf * c1, kf * c0, -kr * c3, -kr * c2};
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double sgn = i < 2 ? -1.0 : 1.0;
       const int k = sp[i];
       sl(sl.W + k) += sgn * q;
       sl(sl.AT + k) += sgn * dqdT;
       if (k < NS)
+#pragma unroll
         for (int l = 0; l < 4; ++l)
           if (sp[l] < NS) sl.a(k, sp[l]) += sgn * dq[l] * m->invW[sp[l]];
     }
   }
   // A = I - h W_k (d(sum nu q)/dy_m + aT_k dT/dy_m); w_k = W_k (sum nu q)_k
   const double irc = 1.0 / (rho * cv);
+  double dTdy[NS];
+#pragma unroll
+  for (int c = 0; c < NS; ++c) dTdy[c] = -m->Rk[c] * T * (sl(sl.HR + c) - 1.0) * irc;
+#pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double hW = h * m->W[k], aT = sl(sl.AT + k);
-    for (int c = 0; c < NS; ++c) {
-      const double dTdy = -m->Rk[c] * T * (sl(sl.HR + c) - 1.0) * irc;
-      sl.a(k, c) = (k == c ? 1.0 : 0.0) - hW * (sl.a(k, c) + aT * dTdy);
-    }
+#pragma unroll
+    for (int c = 0; c < NS; ++c) sl.a(k, c) = (k == c ? 1.0 : 0.0) - hW * (sl.a(k, c) + aT * dTdy[c]);
     sl(sl.W + k) *= m->W[k];
   }
 }
@@ -1325,9 +1406,11 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
 // A x = G in place (x in G) by Gaussian elimination with partial pivoting.
 template <int NS>
 __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
+#pragma unroll
   for (int col = 0; col < NS; ++col) {
     int piv = col;
     double best = fabs(sl.a(col, col));
+#pragma unroll
     for (int r = col + 1; r < NS; ++r) {
       const double v = fabs(sl.a(r, col));
       if (v > best) {
@@ -1336,6 +1419,7 @@ __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
       }
     }
     if (piv != col) {
+#pragma unroll
       for (int c = col; c < NS; ++c) {
         const double t = sl.a(col, c);
         sl.a(col, c) = sl.a(piv, c);
@@ -1346,16 +1430,18 @@ __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
       sl(sl.G + piv) = t;
     }
     const double inv = 1.0 / sl.a(col, col);
+#pragma unroll
     for (int r = col + 1; r < NS; ++r) {
       const double f = sl.a(r, col) * inv;
-      if (f != 0.0) {
-        for (int c = col + 1; c < NS; ++c) sl.a(r, c) -= f * sl.a(col, c);
-        sl(sl.G + r) -= f * sl(sl.G + col);
-      }
+#pragma unroll
+      for (int c = col + 1; c < NS; ++c) sl.a(r, c) -= f * sl.a(col, c);
+      sl(sl.G + r) -= f * sl(sl.G + col);
     }
   }
+#pragma unroll
   for (int r = NS - 1; r >= 0; --r) {
     double x = sl(sl.G + r);
+#pragma unroll
     for (int c = r + 1; c < NS; ++c) x -= sl.a(r, c) * sl(sl.G + c);
     sl(sl.G + r) = x / sl.a(r, r);
   }
@@ -1367,66 +1453,91 @@ __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
 // densities b (rho, rho u, rho E fixed, hence rho and the internal energy):
 // stop one iteration after the first whose largest update is at most
 // 1e-13 rho (at most 40; else NSDC_ERR_IMPLICIT).  Writes X = w(y*).
-template <int NS>
-__global__ __launch_bounds__(256) void k_mr2_imp(const BoxDev *__restrict__ boxes,
-                                                 const Item *__restrict__ items, int nitems, TileShape ts,
-                                                 FRef Ucur, Mr2Imp a, const DevMech *__restrict__ m, int *err) {
+// LDS: up to 9 species, the slots in LDS, one wave per workgroup making as
+// many passes over the interior tile as it has waves of cells; otherwise the
+// workspace slots, one lane per cell of the tile.
+template <int NS, bool LDS>
+__global__ __launch_bounds__(LDS ? 64 : 256) void k_mr2_imp(const BoxDev *__restrict__ boxes,
+                                                            const Item *__restrict__ items, int nitems,
+                                                            TileShape ts, FRef Ucur, Mr2Imp a,
+                                                            const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
-  const Mr2Slot<NS> sl{a.J + (long long)blockIdx.x * blockDim.x + threadIdx.x, a.jstride};
+  __shared__ double slot_sh[LDS ? NSDC_MR2_SLOT(NS) * 64 : 1];
+  const Mr2Slot<NS> sl = LDS ? Mr2Slot<NS>{slot_sh + threadIdx.x, 64}
+                             : Mr2Slot<NS>{a.J + (long long)blockIdx.x * blockDim.x + threadIdx.x, a.jstride};
+  const int tcells = ts.tx * ts.ty * ts.tz;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
-    int x, y, z;
-    tile_cell(w, ts, x, y, z);
-    if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
-    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
-    const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
-    const long long i = ((long long)z * b.ny + y) * b.nx + x;
-    const long long o2 = b.offI * NU + i, o1 = b.offI * NS + i;
-    const double *U = Ucur.get(w.box, b.offS * NU);
-    double Us[5];
-    for (int q = 0; q < NU; ++q) {
-      double v = U[q * nS + s];
-      for (int j = 0; j < a.n2; ++j) v += a.c2[j] * a.F2[j][o2 + q * nI];
-      if (q >= 5) {
-        for (int j = 0; j < a.n1; ++j) v += a.c1[j] * a.F1[j][o1 + (q - 5) * nI];
-        v -= a.h * a.F1right[o1 + (q - 5) * nI];
-        sl(sl.B + q - 5) = v;
-        sl(sl.Y + q - 5) = v;
+    for (int pass = 0; pass < (LDS ? (tcells + 63) / 64 : 1); ++pass) {
+      int x, y, z;
+      if constexpr (LDS) {
+        const int lin = pass * 64 + (int)threadIdx.x;
+        if (lin >= tcells) continue;
+        x = w.x0 + lin % ts.tx;
+        y = w.y0 + (lin / ts.tx) % ts.ty;
+        z = w.z0 + lin / (ts.tx * ts.ty);
       } else {
-        Us[q] = v;
+        tile_cell(w, ts, x, y, z);
       }
-    }
-    const double rho = Us[0], ir = 1.0 / rho;
-    const double e = Us[4] * ir - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2] + Us[3] * Us[3]) * ir * ir;
-    double T = 1000.0, Y[NS];
-    int errs = rho > 0.0 ? 0 : NSDC_ERR_RHO;
-    bool conv = false, done = false;
-    for (int itn = 0; itn < 40 && !done; ++itn) {
-      for (int k = 0; k < NS; ++k) Y[k] = sl(sl.Y + k) * ir;
+      if (x >= b.nx || y >= b.ny || z >= b.nz) continue;
+      const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+      const long long s = ((long long)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+      const long long i = ((long long)z * b.ny + y) * b.nx + x;
+      const long long o2 = b.offI * NU + i, o1 = b.offI * NS + i;
+      const double *U = Ucur.get(w.box, b.offS * NU);
+      double Us[5], yv[NS], bv[NS];
+#pragma unroll
+      for (int q = 0; q < NU; ++q) {
+        double v = U[q * nS + s];
+        for (int j = 0; j < a.n2; ++j) v += a.c2[j] * a.F2[j][o2 + q * nI];
+        if (q >= 5) {
+          for (int j = 0; j < a.n1; ++j) v += a.c1[j] * a.F1[j][o1 + (q - 5) * nI];
+          v -= a.h * a.F1right[o1 + (q - 5) * nI];
+          bv[q - 5] = v;
+          yv[q - 5] = v;
+        } else {
+          Us[q] = v;
+        }
+      }
+      const double rho = Us[0], ir = 1.0 / rho;
+      const double e = Us[4] * ir - 0.5 * (Us[1] * Us[1] + Us[2] * Us[2] + Us[3] * Us[3]) * ir * ir;
+      double T = 1000.0, Y[NS];
+      int errs = rho > 0.0 ? 0 : NSDC_ERR_RHO;
+      bool conv = false, done = false;
+      for (int itn = 0; itn < 40 && !done; ++itn) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Y[k] = yv[k] * ir;
+        errs |= temperature<NS>(m, Y, e, T, T);
+        double cv = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
+        mr2_rates_jacobian<NS>(m, sl, yv, rho, T, cv, a.h);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) sl(sl.G + k) = yv[k] - a.h * sl(sl.W + k) - bv[k];
+        mr2_solve<NS>(sl);
+        double dmax = 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const double d = sl(sl.G + k);
+          yv[k] -= d;
+          dmax = fmax(dmax, fabs(d));
+        }
+        done = conv;
+        conv = !(dmax > 1e-13 * rho);   // (a NaN update never converges)
+      }
+      if (!done) errs |= NSDC_ERR_IMPLICIT;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) Y[k] = yv[k] * ir;
       errs |= temperature<NS>(m, Y, e, T, T);
       double cv = 0.0;
+#pragma unroll
       for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
-      mr2_rates_jacobian<NS>(m, sl, rho, T, cv, a.h);
-      for (int k = 0; k < NS; ++k) sl(sl.G + k) = sl(sl.Y + k) - a.h * sl(sl.W + k) - sl(sl.B + k);
-      mr2_solve<NS>(sl);
-      double dmax = 0.0;
-      for (int k = 0; k < NS; ++k) {
-        const double d = sl(sl.G + k);
-        sl(sl.Y + k) -= d;
-        dmax = fmax(dmax, fabs(d));
-      }
-      done = conv;
-      conv = !(dmax > 1e-13 * rho);   // (a NaN update never converges)
+      mr2_rates_jacobian<NS>(m, sl, yv, rho, T, cv, a.h);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) a.X[o1 + k * nI] = sl(sl.W + k);
+      if (errs) atomicOr(err, errs);
     }
-    if (!done) errs |= NSDC_ERR_IMPLICIT;
-    for (int k = 0; k < NS; ++k) Y[k] = sl(sl.Y + k) * ir;
-    errs |= temperature<NS>(m, Y, e, T, T);
-    double cv = 0.0;
-    for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
-    mr2_rates_jacobian<NS>(m, sl, rho, T, cv, a.h);
-    for (int k = 0; k < NS; ++k) a.X[o1 + k * nI] = sl(sl.W + k);
-    if (errs) atomicOr(err, errs);
   }
 }
 
@@ -1494,15 +1605,25 @@ struct Launch {
   static void vgrad(const LaunchCtx &c, const double *P, double *G) {
     prof_begin(c.prof, K_VGRAD, c.stream);
     hipLaunchKernelGGL(k_vgrad<NS>, dim3(grid_for(c.nS, c.cap)), dim3(c.tsS.tx * c.tsS.ty * c.tsS.tz), 0,
-                       c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, G);
+                       c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, G, c.mech);
     prof_end(c.prof, K_VGRAD, c.stream);
   }
   template <int D, bool FIXED, bool REF, bool WIDE>
   static void dir_k(const LaunchCtx &c, FRef U, const double *P, const double *G, FRef F, unsigned parts) {
     const TileShape ts = c.tsD[D];
     const dim3 grid(grid_for(c.nD[D], c.cap)), block(ts.tx * ts.ty * ts.tz);
-    hipLaunchKernelGGL((k_dir<NS, D, FIXED, REF, WIDE>), grid, block, 0, c.stream, c.boxes, c.itemsD[D], c.nD[D], ts,
-                       U, P, G, F, parts, c.mech);
+    hipLaunchKernelGGL((k_dir<NS, D, FIXED, REF, WIDE, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[D],
+                       c.nD[D], ts, U, P, G, F, parts, c.mech);
+    // the boundary layers of boxes with physical boundaries along D (the
+    // wide stencil is rejected with them)
+    if constexpr (!WIDE) {
+      if (c.nB[D] > 0) {
+        const TileShape tb = c.tsB[D];
+        hipLaunchKernelGGL((k_dir<NS, D, FIXED, REF, false, true>), dim3(grid_for(c.nB[D], c.cap)),
+                           dim3(tb.tx * tb.ty * tb.tz), 0, c.stream, c.boxes, c.itemsB[D], c.nB[D], tb, U, P, G, F,
+                           parts, c.mech);
+      }
+    }
   }
   template <bool FIXED, bool REF, bool WIDE>
   static void dir_d(const LaunchCtx &c, int d, FRef U, const double *P, const double *G, FRef F, unsigned parts) {
@@ -1557,14 +1678,20 @@ struct Launch {
   }
   static void mr2_imp(const LaunchCtx &c, FRef Ucur, const Mr2Imp &a) {
     // the lanes' workspace slots bound the grid
-    // the lanes' workspace slots bound the grid (the workspace holds
-    // NSDC_MR2_MAXWG workgroups of the interior tile)
-    const int grid = grid_for(grid_for(c.nI, c.cap), NSDC_MR2_MAXWG), block = c.tsI.tx * c.tsI.ty * c.tsI.tz;
-    Mr2Imp b = a;
-    b.jstride = (long long)grid * block;
     prof_begin(c.prof, K_MR2_IMP, c.stream);
-    hipLaunchKernelGGL(k_mr2_imp<NS>, dim3(grid), dim3(block), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Ucur,
-                       b, c.mech, c.err);
+    if constexpr (NS <= 9) {
+      // the Newton matrices in LDS: one wave per workgroup
+      hipLaunchKernelGGL((k_mr2_imp<NS, true>), dim3(grid_for(c.nI, c.cap)), dim3(64), 0, c.stream, c.boxes,
+                         c.itemsI, c.nI, c.tsI, Ucur, a, c.mech, c.err);
+    } else {
+      // the lanes' workspace slots bound the grid (the workspace holds
+      // NSDC_MR2_MAXWG workgroups of the interior tile)
+      const int grid = grid_for(grid_for(c.nI, c.cap), NSDC_MR2_MAXWG), block = c.tsI.tx * c.tsI.ty * c.tsI.tz;
+      Mr2Imp b = a;
+      b.jstride = (long long)grid * block;
+      hipLaunchKernelGGL((k_mr2_imp<NS, false>), dim3(grid), dim3(block), 0, c.stream, c.boxes, c.itemsI, c.nI,
+                         c.tsI, Ucur, b, c.mech, c.err);
+    }
     prof_end(c.prof, K_MR2_IMP, c.stream);
   }
   static void mr2_node(const LaunchCtx &c, FRef Ucur, FRef Unext, const Mr2Node &a) {

@@ -31,6 +31,9 @@ struct LaunchCtx {
   const Item *itemsD[3];   // interior lists of the stencil passes, direction D fastest
   int nD[3];
   TileShape tsD[3];
+  const Item *itemsB[3];   // boundary layers of the directions with physical boundaries
+  int nB[3];
+  TileShape tsB[3];
   int nI, nS, nG;
   TileShape tsI, tsS;
   int cap;

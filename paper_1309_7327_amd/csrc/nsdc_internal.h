@@ -38,6 +38,13 @@ struct DevMech {
   double B[9][9];             // face-difference matrix B_oc = M_{o-1,c-1} - M_{o,c}
   double e2tab[64];           // 2^(j/64), j = 0..63 (correctly rounded), for the rate exponentials
   int ref;                    // species diffusion: -1 correction velocity, k >= 0 reference species k
+  // stencils near a physical boundary (Section 2.5), variant v = b + 4 high
+  // for a cell b = 0..3 cells from the boundary below (high = 0) or above
+  // (high = 1), on the nine samples centred on the cell: first-derivative
+  // weights of the advective and the diffusive terms (times 1/h), and the
+  // matrix of the second-derivative pairs, (a u_x)_x = sum_oc a_o K_oc u_c / h^2
+  double bwA[8][9], bwD[8][9];
+  double bK[8][9][9];
 };
 
 // One box of a batch.  offS / offI: offsets (in cells) of this box inside
@@ -46,6 +53,7 @@ struct DevMech {
 struct BoxDev {
   int nx, ny, nz;
   int sx, sy, sz;
+  int np;   // bit d: physical boundaries along d (the box_desc's nonperiodic)
   long long offS, offI;
   double idx[3], idx2[3];
 };
@@ -131,9 +139,10 @@ struct FinePtrs {
 //   U_p + sum_j c1_j F1_j + sum_j c2_j F2_j - h F1_{p+1}
 // (c1, c2: dt times the interval's sums of S21 and S22 rows), h the coarse
 // interval; the other components are those of the same sum.  X = w(y*).
-// Each lane owns a slot of the workspace J (entry i at J[lane + i jstride],
-// NSDC_MR2_SLOT(ns) entries) for its Newton matrix and vectors.
-#define NSDC_MR2_SLOT(ns) ((ns) * (ns) + 8 * (ns) + 5)
+// Above nine species each lane owns a slot of the workspace J (entry i at
+// J[lane + i jstride], NSDC_MR2_SLOT(ns) entries) for its Newton matrix and
+// runtime-indexed vectors; up to nine species they live in LDS.
+#define NSDC_MR2_SLOT(ns) ((ns) * (ns) + 6 * (ns) + 5)
 #define NSDC_MR2_MAXWG 512   // workgroups of the implicit kernel (the lane slots)
 struct Mr2Imp {
   const double *F1[8];              // f1 at the coarse nodes, iteration k

@@ -25,7 +25,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 class BoxDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("ng", ctypes.c_int),
-                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("nonperiodic", ctypes.c_int)]
 
 
 class MechanismDesc(ctypes.Structure):
@@ -94,8 +95,9 @@ class NarrowSDCError(RuntimeError):
         self.code = code
 
 
-def box(nx, ny, nz, dx, dy=None, dz=None):
-    return BoxDesc(nx, ny, nz, NG, dx, dx if dy is None else dy, dx if dz is None else dz)
+def box(nx, ny, nz, dx, dy=None, dz=None, nonperiodic=0):
+    """nonperiodic: bit d (1 x, 2 y, 4 z) for physical boundaries along d."""
+    return BoxDesc(nx, ny, nz, NG, dx, dx if dy is None else dy, dx if dz is None else dz, int(nonperiodic))
 
 
 def scheme(n_coarse=4, sweeps=6, n_fine=0, fine_repeat=1, mode=1):

@@ -17,6 +17,9 @@
   box64_adjoint   64^3, 9/21, vector-Jacobian product of the right-hand side.
   box64_sdc_resid 64^3, 9/21, single-rate SDC of up to 12 sweeps per step
                   with the residual early exit (ratio 1.5), 5 steps.
+  box128_mrsdc_xwall  box128_mrsdc with physical boundaries at both ends of x
+                  (the boundary stencils of Section 2.5) instead of periodic
+                  wrap-around.
   box128_mrsdc2   box128_mrsdc's flame with multirate mode 2: the chemistry
                   implicit on 5 Gauss-Lobatto coarse nodes, advection-
                   diffusion on 3 Gauss-Lobatto nodes repeated twice in each
@@ -58,6 +61,9 @@ WORKLOADS = {
     "box64_sdc_resid": dict(shape=(64, 64, 64), dx=1e-4, mech="mech9", recipe="sines", seed=5,
                             scheme=dict(kind="sdc", n_coarse=4, sweeps=12, n_fine=0), steps=5,
                             residual_ratio=1.5),
+    "box128_mrsdc_xwall": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9", recipe="turb", seed=2, kmax=16,
+                               scheme=dict(kind="mrsdc", n_coarse=4, n_fine=5, fine_repeat=1, sweeps=6), steps=10,
+                               nonperiodic=1),
     "box128_mrsdc2": dict(shape=(128, 128, 128), dx=1e-4, mech="mech9", recipe="turb", seed=2, kmax=16,
                           scheme=dict(kind="mrsdc", n_coarse=5, n_fine=3, fine_repeat=2, sweeps=4, mode=2),
                           steps=5, cfl=2.0),
