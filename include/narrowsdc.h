@@ -198,10 +198,10 @@ int set_wide_stencil(sdc_context *ctx, int enable);
 /* Kernel choice for the fine sub-steps of a multirate sweep (eq. mrupdate),
  * a tuning switch that leaves results unchanged bit for bit: enable != 0
  * (default) runs them as one kernel per coarse interval wherever the scheme
- * has four coarse nodes and four fine sub-steps per interval and the
- * mechanism at most nine species (the quadrature increments stay in
- * registers); enable = 0, and every other case, uses a streaming quadrature
- * kernel followed by the sub-step kernel. */
+ * has four coarse nodes and four fine sub-steps per interval (the quadrature
+ * increments stay on chip; above nine species the two lanes of a cell split
+ * them by species); enable = 0, and every other case, uses a streaming
+ * quadrature kernel followed by the sub-step kernel. */
 int sdc_set_fused_fine(sdc_context *ctx, int enable);
 
 /* SDC residual early exit (the residual of eq. residual, R^k = U_0 +

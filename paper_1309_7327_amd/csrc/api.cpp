@@ -124,7 +124,10 @@ struct Plan {
   // the boundary layers (4 cells deep) of the directions with physical
   // boundaries: work items of the boundary variant of the stencil passes
   int nB[3] = {0, 0, 0};
-  TileShape tsB[3] = {{4, 8, 8}, {16, 4, 4}, {16, 4, 4}};
+  // (one plane along the direction per tile row, so every wave's cells
+  // share their distance from the boundary and the stencil tables' reads
+  // are uniform)
+  TileShape tsB[3] = {{1, 16, 16}, {64, 1, 4}, {64, 4, 1}};
   int cap = 0;                 // workgroups per launch (0: one per work item)
   double **d_Utab = nullptr;
   std::vector<double *> Uptrs;
@@ -259,7 +262,7 @@ struct sdc_context {
   bool use_graph = false;
   // SDC residual early exit (single-rate sdc_step): ratio 0 = off
   bool wide = false;                    // wide-stencil second derivatives
-  bool fused_fine = true;               // one-kernel multirate fine sub-steps (4 sub-steps, <= 9 species)
+  bool fused_fine = true;               // one-kernel multirate fine sub-steps (4 coarse nodes, 4 sub-steps)
   double resid_ratio = 0.0;
   double *d_resid = nullptr;            // [NSDC_RESID_BLOCKS + 1][2 nU max] partial maxima, result
   std::vector<double> resid_hist;       // residuals measured by the last sdc_step call
@@ -437,8 +440,8 @@ void plan_layout(const sdc_context *c, Plan *p, std::vector<BoxDev> &hb, std::ve
         for (int x = 0; x < d.sx; x += tS.tx) iS.push_back(Item{b, x, y, z});
     const long long ng = (long long)d.sx * d.sy * d.sz - (long long)d.nx * d.ny * d.nz;
     for (long long g = 0; g < ng; g += 256) iG.push_back(Item{b, (int)g, 0, 0});
-    // boundary layers: tiles 4 cells deep at both ends of each direction
-    // with physical boundaries (at least 8 cells, so the two are disjoint)
+    // boundary layers: the 4 planes at both ends of each direction with
+    // physical boundaries (at least 8 cells, so the two sets are disjoint)
     const int n3[3] = {d.nx, d.ny, d.nz};
     for (int dd = 0; dd < 3; ++dd) {
       if (!((d.np >> dd) & 1)) continue;
@@ -592,7 +595,7 @@ struct WsLayout {
 
 WsLayout ws_layout(const Plan *p, int ns, const sdc_scheme *s) {
   WsLayout w{};
-  const int nU = 5 + ns, nP = 8 + 3 * ns;
+  const int nU = 5 + ns, nP = 9 + 3 * ns;
   const int M1 = s->n_coarse - 1;
   if (s->n_fine != 0 && s->mode == 2) {
     // mode 2: F1 = chemistry at the coarse nodes (ns per cell), F2 =
@@ -1264,7 +1267,7 @@ int rhs_eval(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsig
   rc = get_plan(c, 1, box, nullptr, &pl);
   if (rc) return rc;
   const int ns = c->ops->ns;
-  const size_t need = ((size_t)pl->totS * (8 + 3 * ns + 9) + 64) * sizeof(double);
+  const size_t need = ((size_t)pl->totS * (9 + 3 * ns + 9) + 64) * sizeof(double);
   if (need > c->scratch_bytes) {
     HIPCHECK(c, hipStreamSynchronize((hipStream_t)stream));
     if (c->scratch) (void)hipFree(c->scratch);
@@ -1274,7 +1277,7 @@ int rhs_eval(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsig
     c->scratch_bytes = need;
   }
   double *P = c->scratch;
-  double *G = P + ((((size_t)pl->totS * (8 + 3 * ns)) + 31) & ~size_t(31));
+  double *G = P + ((((size_t)pl->totS * (9 + 3 * ns)) + 31) & ~size_t(31));
   const LaunchCtx l = make_lc(c, pl, (hipStream_t)stream);
   eval_rhs_g(c->ops, l, FRef{U, nullptr}, P, G, FRef{dUdt, nullptr}, parts);
   HIPCHECK(c, hipGetLastError());
@@ -1304,7 +1307,7 @@ int rhs_eval_static(sdc_context *c, const box_desc *box, double *U, double *dUdt
   auto up256 = [](size_t n) { return (n + 255) & ~size_t(255); };
   const size_t off_items = up256(sizeof(BoxDev));
   const size_t off_P = up256(off_items + sizeof(Item) * items.size());
-  const size_t off_G = up256(off_P + sizeof(double) * (size_t)p.totS * (8 + 3 * ns));
+  const size_t off_G = up256(off_P + sizeof(double) * (size_t)p.totS * (9 + 3 * ns));
   const size_t need = off_G + sizeof(double) * ((size_t)p.totS * 9 + 64);
   if (need > NSDC_STATIC_SCRATCH_BYTES)
     return fail(c, SDC_EINVAL, "box needs " + std::to_string(need) + " bytes of static scratch, more than its " +
@@ -1642,7 +1645,7 @@ struct VjpLayout {
 };
 VjpLayout vjp_layout(const Plan *p, int ns, int nr, int cap) {
   VjpLayout w{};
-  const int nU = 5 + ns, nP = 8 + 3 * ns;
+  const int nU = 5 + ns, nP = 9 + 3 * ns;
   size_t off = 0;
   auto take = [&](size_t n) {
     size_t o = off;

@@ -185,6 +185,7 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
     P[L::PMU * nS + s] = mu;
     P[L::PLAM * nS + s] = lam;
     P[L::PRD * nS + s] = lam / cp;
+    P[L::PWB * nS + s] = Wbar;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       P[(L::PY + k) * nS + s] = Y[k];
@@ -305,7 +306,8 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
     const int cD = D == 0 ? x : (D == 1 ? y : z), nDd = D == 0 ? b.nx : (D == 1 ? b.ny : b.nz);
     int vb = 0;
     if constexpr (BND) {
-      vb = min(cD, nDd - 1 - cD) + (nDd - 1 - cD < cD ? 4 : 0);
+      // (the boundary work lists give every wave cells of one plane along D)
+      vb = __builtin_amdgcn_readfirstlane(min(cD, nDd - 1 - cD) + (nDd - 1 - cD < cD ? 4 : 0));
     } else {
       if (((b.np >> D) & 1) && (cD < 4 || cD >= nDd - 4)) continue;
     }
@@ -552,8 +554,14 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
       // species diffusion (pairs (rho D_k, X_k), (rho D_k (X_k-Y_k)/p, p) and
       // the energy pairs with h_k) and the correction velocity V_c,D, div V_c
       {
-        double rd[9], wp[9], u9[9], v[9], g[9];
+        // X_k lines formed from the Y_k lines and the mean molecular weight
+        // (the same bits as the stored X_k, one line fewer per species),
+        // except along x with up to nine species, where the extra live
+        // registers of the Wbar line spill
+        constexpr bool XLINE = !WIDE && !REF && (NS > 9 || D != 0);
+        double rd[9], wp[9], u9[9], v[9], g[9], wb9[XLINE ? 9 : 1];
         line(P + L::PRD * nS, rd);
+        if constexpr (XLINE) line(P + L::PWB * nS, wb9);
         if constexpr (WIDE) {
           double w[17];
           line17(P + L::PP * nS, w);
@@ -643,6 +651,13 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
               xpair(P + (L::PX + k) * nS, u9, v);
               line(P + (L::PY + k) * nS, y9);
               line(P + (L::PH + k) * nS, g);
+            } else if constexpr (XLINE) {
+              // X_k = Y_k Wbar / W_k as the primitives kernel forms it
+              line(P + (L::PY + k) * nS, y9);
+              line(P + (L::PH + k) * nS, g);
+#pragma unroll
+              for (int o = 0; o < 9; ++o) u9[o] = y9[o] * wb9[o] * m->invW[k];
+              BV(u9, v);
             } else {
               // all three lines in flight before B X_k is formed
               line(P + (L::PX + k) * nS, u9);
@@ -684,9 +699,17 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
               line(U + (5 + k) * nS, u9);
               spc(k) -= DAP(u9, ud);
             }
-            xpair(P + (L::PX + k) * nS, u9, v);
+            if constexpr (!XLINE) {
+              xpair(P + (L::PX + k) * nS, u9, v);
+              line(P + (L::PY + k) * nS, g);
+            } else {
+              // X_k = Y_k Wbar / W_k as the primitives kernel forms it
+              line(P + (L::PY + k) * nS, g);
+#pragma unroll
+              for (int o = 0; o < 9; ++o) u9[o] = g[o] * wb9[o] * m->invW[k];
+              BV(u9, v);
+            }
             const double DX = DD(u9);
-            line(P + (L::PY + k) * nS, g);
             const double dXY4 = u9[4] - g[4];
 #pragma unroll
             for (int o = 0; o < 9; ++o) u9[o] -= g[o];
@@ -1159,6 +1182,227 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
 #pragma unroll
       for (int q = 0; q < NU; ++q)
         if ((q & 1) == sub) (Uo + q * nS)[s] = Uc[q];
+    }
+  }
+}
+
+// k_mr_src and k_mr_pair in one kernel for four coarse nodes and four fine
+// sub-steps above nine species: the increments of eq. (mrupdate) are formed in
+// registers with k_mr_src's arithmetic and consumed by k_mr_pair's sub-steps,
+// so they never reach HBM.  The lanes of a pair (32 apart in a wave) split the
+// species: lane sub owns the species k with k mod 2 = sub, their 4 increments
+// and partial densities; both lanes run the five non-species components
+// through the sub-steps (their increments need only f1).  Before every
+// temperature solve the pair exchanges its species densities through the
+// cell's LDS column, so both lanes solve with every density and the same
+// operations as k_mr_pair: the results equal the two-kernel form bit for bit.
+template <int NS>
+__global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restrict__ boxes,
+                                                          const Item *__restrict__ items, int nitems,
+                                                          TileShape ts, FRef Uin, FRef Uout,
+                                                          const FineCoef *__restrict__ fc, FinePtrs fp,
+                                                          const DevMech *__restrict__ m, int *err) {
+  constexpr int NU = 5 + NS, CS = 128, A = (NS + 1) * CS, NQ = 4;
+  constexpr int NK = (NS + 1) / 2;   // species per lane (the even lane one more for odd NS)
+  __shared__ double col[3 * A];
+  __shared__ double tab[64];
+  __shared__ int rsp[NSDC_NRMAX][4];
+  __shared__ double rco[NSDC_NRMAX][4];
+  const int nr = m->nr;
+  for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = m->e2tab[j];
+  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+    rsp[j][0] = m->rs[j][0] * CS;
+    rsp[j][1] = m->rs[j][1] * CS;
+    rsp[j][2] = m->ps[j][0] * CS;
+    rsp[j][3] = m->ps[j][1] * CS;
+    rco[j][0] = m->lnA[j];
+    rco[j][1] = m->beta[j];
+    rco[j][2] = m->EaR[j];
+    rco[j][3] = (double)m->dnu[j];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, slot = (threadIdx.x >> 6) * 32 + (lane & 31), sub = lane >> 5;
+  double *sh = col + slot;
+  // as in k_mr_pair
+  auto production_pair = [&](double rho, double T, const double *Y, double *wdot) {
+    const double lnT = log(T), invT = 1.0 / T;
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      sh[k * CS] = rho * Y[k] * m->invW[k];
+      sh[A + k * CS] = g_RT(m, k, T, invT, lnT);
+      sh[2 * A + k * CS] = 0.0;
+    }
+    sh[NS * CS] = 1.0;
+    sh[A + NS * CS] = 0.0;
+    sh[2 * A + NS * CS] = 0.0;
+    wave_sync();
+    const double lnRTp = lnT + LN_RU_PREF;
+#pragma unroll 4
+    for (int j = sub; j < nr; j += 2) {
+      const int r0 = rsp[j][0], r1 = rsp[j][1], p0 = rsp[j][2], p1 = rsp[j][3];
+      const double lnkf = rco[j][0] + rco[j][1] * lnT - rco[j][2] * invT;
+      const double dg = (sh[A + p0] + sh[A + p1]) - (sh[A + r0] + sh[A + r1]);
+      const double kf = exp_tab(lnkf, tab);
+      const double kr = exp_tab(lnkf + dg + rco[j][3] * lnRTp, tab);
+      const double q = kf * sh[r0] * sh[r1] - kr * sh[p0] * sh[p1];
+      atomicAdd(sh + 2 * A + r0, -q);
+      atomicAdd(sh + 2 * A + r1, -q);
+      atomicAdd(sh + 2 * A + p0, q);
+      atomicAdd(sh + 2 * A + p1, q);
+    }
+    wave_sync();
+    // this lane's species only
+#pragma unroll
+    for (int n = 0; n < NK; ++n) {
+      const int k = 2 * n + sub;
+      if (k < NS) wdot[n] = sh[2 * A + k * CS] * m->W[k];
+    }
+  };
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item w = items[it];
+    const BoxDev b = boxes[w.box];
+    const long long nS = (long long)b.sx * b.sy * b.sz, nI = (long long)b.nx * b.ny * b.nz;
+    const long long o1 = b.offI * NU, o2 = b.offI * NS;
+    const double *Ui = Uin.get(w.box, b.offS * NU);
+    double *Uo = Uout.get(w.box, b.offS * NU);
+    auto F1 = [&](int sl, int q) { return fp.F1base + (sl * fp.f1slot + o1 + q * nI); };
+    auto F2 = [&](int sl, int k) { return fp.F2base + (sl * fp.f2slot + o2 + k * nI); };
+    const int n1 = fc->n1, nf = fc->nfine;
+    const double dt = fp.dt;
+    for (int h = 0; h < 2; ++h) {
+      const int cell = h * (int)(blockDim.x >> 1) + slot;
+      const int x = w.x0 + cell % ts.tx, y = w.y0 + (cell / ts.tx) % ts.ty, z = w.z0 + cell / (ts.tx * ts.ty);
+      if (cell >= ts.tx * ts.ty * ts.tz || x >= b.nx || y >= b.ny || z >= b.nz) continue;
+      const unsigned s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+      const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
+      // increments of component q for the NQ sub-steps, k_mr_src's arithmetic
+      auto increments = [&](int q, double *inc) {
+        asm volatile("" ::: "memory");
+        double f1[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) f1[j] = j < n1 ? F1(fp.F1old[j], q)[i] : 0.0;
+        const double dF1 = F1(fp.F1new_p, q)[i] - F1(fp.F1old_p, q)[i];
+        double g[NQ + 1];
+        if (q >= 5) {
+#pragma unroll
+          for (int j = 0; j <= NQ; ++j) g[j] = F2(fp.F2old[j], q - 5)[i];
+        }
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+          const double dtq = fc->dtq[r] * dt;
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc += fc->S21[r][j] * f1[j];
+          double v = dtq * dF1 + dt * acc;
+          if (q >= 5) {
+            const int jlo = fc->jlo[r];
+            double s22 = 0.0;
+#pragma unroll
+            for (int j = 0; j <= NQ; ++j) {
+              const int jj = j - jlo;
+              if (jj >= 0 && jj < nf) s22 += fc->S22[r][jj] * g[j];
+            }
+            v += dt * s22 - dtq * g[r];
+          }
+          inc[r] = v;
+        }
+      };
+      // the non-species components through the sub-steps (the chemistry
+      // leaves them alone): keep the density and internal energy each
+      // temperature solve needs, formed as cell_state forms them, and the
+      // final values
+      double Un[5], rho_r[NQ + 1], e_r[NQ + 1];
+      {
+        double An[NQ][5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          Un[q] = (Ui + q * nS)[s];
+          double inc[NQ];
+          increments(q, inc);
+#pragma unroll
+          for (int r = 0; r < NQ; ++r) An[r][q] = inc[r];
+        }
+#pragma unroll
+        for (int r = 0; r <= NQ; ++r) {
+          rho_r[r] = Un[0];
+          const double ir = 1.0 / Un[0];
+          const double u0 = Un[1] * ir, u1 = Un[2] * ir, u2 = Un[3] * ir;
+          e_r[r] = Un[4] * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+          if (r < NQ)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) Un[q] += An[r][q] + 0.0;
+        }
+      }
+      double Uk[NK], Ak[NQ][NK];
+#pragma unroll
+      for (int n = 0; n < NK; ++n) {
+        const int k = 2 * n + sub;
+        if (k < NS) {
+          Uk[n] = (Ui + (5 + k) * nS)[s];
+          double inc[NQ];
+          increments(5 + k, inc);
+#pragma unroll
+          for (int r = 0; r < NQ; ++r) Ak[r][n] = inc[r];
+        } else {
+          Uk[n] = 0.0;
+#pragma unroll
+          for (int r = 0; r < NQ; ++r) Ak[r][n] = 0.0;
+        }
+      }
+      // both lanes' species densities through the cell's column, then the
+      // temperature solve of sub-step r as cell_state does it
+      auto state = [&](int r, double &rho, double *Y, double &T, double T0) {
+        wave_sync();   // the previous readers of the column are done
+#pragma unroll
+        for (int n = 0; n < NK; ++n)
+          if (2 * n + sub < NS) sh[2 * A + (2 * n + sub) * CS] = Uk[n];
+        wave_sync();
+        rho = rho_r[r];
+        const double ir = 1.0 / rho;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) Y[k] = sh[2 * A + k * CS] * ir;
+        int e = rho > 0.0 ? 0 : NSDC_ERR_RHO;
+        e |= temperature<NS>(m, Y, e_r[r], T, T0);
+        return e;
+      };
+      int errs = 0;
+      double Tprev = 1000.0;
+      for (int qq = 0; qq < NQ; ++qq) {
+        double f2[NK];
+        if (qq == 0 && fp.q0_known) {
+#pragma unroll
+          for (int n = 0; n < NK; ++n)
+            if (2 * n + sub < NS) f2[n] = F2(fp.F2old[0], 2 * n + sub)[i];
+        } else {
+          double rho, Y[NS], T;
+          errs |= state(qq, rho, Y, T, Tprev);
+          Tprev = T;
+          production_pair(rho, T, Y, f2);
+#pragma unroll
+          for (int n = 0; n < NK; ++n)
+            if (2 * n + sub < NS) F2(fp.F2new[qq], 2 * n + sub)[i] = f2[n];
+        }
+        const double dtq = fc->dtq[qq] * dt;
+#pragma unroll
+        for (int n = 0; n < NK; ++n)
+          if (2 * n + sub < NS) Uk[n] += Ak[qq][n] + dtq * f2[n];
+      }
+      if (fp.eval_last) {
+        double rho, Y[NS], T, f2[NK];
+        errs |= state(NQ, rho, Y, T, Tprev);
+        production_pair(rho, T, Y, f2);
+#pragma unroll
+        for (int n = 0; n < NK; ++n)
+          if (2 * n + sub < NS) F2(fp.F2new[NQ], 2 * n + sub)[i] = f2[n];
+      }
+      if (errs) atomicOr(err, errs);
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+        if ((q & 1) == sub) (Uo + q * nS)[s] = Un[q];
+#pragma unroll
+      for (int n = 0; n < NK; ++n)
+        if (2 * n + sub < NS) (Uo + (5 + 2 * n + sub) * nS)[s] = Uk[n];
     }
   }
 }
@@ -1708,6 +1952,15 @@ struct Launch {
         prof_begin(c.prof, K_MR_FINE, c.stream);
         hipLaunchKernelGGL(k_mr_fused<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout,
                            fc, fp, c.mech, c.err);
+        prof_end(c.prof, K_MR_FINE, c.stream);
+        return;
+      }
+    }
+    if constexpr (NS > 9) {
+      if (fp.nq == 4 && fp.n1 == 4 && c.fused_fine) {
+        prof_begin(c.prof, K_MR_FINE, c.stream);
+        hipLaunchKernelGGL(k_mr_pair_fused<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin,
+                           Uout, fc, fp, c.mech, c.err);
         prof_end(c.prof, K_MR_FINE, c.stream);
         return;
       }

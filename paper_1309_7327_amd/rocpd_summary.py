@@ -31,7 +31,7 @@ CALIB_BYTES = 1 << 30
 _KINDS = [
     (r"k_prim_to_cons<", "prim_to_cons"), (r"k_ghost<", "ghost"), (r"k_prims<", "prims"),
     (r"k_vgrad<", "vgrad"), (r"k_dir<\d+, 0", "dir_x"), (r"k_dir<\d+, 1", "dir_y"), (r"k_dir<\d+, 2", "dir_z"),
-    (r"k_chem<", "chem"), (r"k_sdc_node<", "sdc_node"), (r"k_mr_step<", "mr_fine"), (r"k_mr_fused<", "mr_fine"), (r"k_mr_pair<", "mr_fine"),
+    (r"k_chem<", "chem"), (r"k_sdc_node<", "sdc_node"), (r"k_mr_step<", "mr_fine"), (r"k_mr_fused<", "mr_fine"), (r"k_mr_pair<", "mr_fine"), (r"k_mr_pair_fused<", "mr_fine"),
     (r"k_mr_src<", "mr_src"), (r"k_mr2_imp<", "mr2_imp"), (r"k_mr2_node<", "sdc_node"),
     (r"k_adj_(coef|g1|g2|g3)<\d+, 0", "dir_adj_x"), (r"k_adj_(coef|g1|g2|g3)<\d+, 1", "dir_adj_y"),
     (r"k_adj_(coef|g1|g2|g3)<\d+, 2", "dir_adj_z"),

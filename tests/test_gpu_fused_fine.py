@@ -1,5 +1,6 @@
-"""Fine sub-steps of the multirate sweep (eq. mrupdate): the one-kernel form
-(quadrature increments kept in registers) against the two-kernel form
+"""Fine sub-steps of the multirate sweep (eq. mrupdate): the one-kernel forms
+(quadrature increments kept in registers; above nine species on paired
+lanes) against the two-kernel form
 (streaming quadrature pass, then the sub-step kernel), through the C-ABI.
 Both evaluate the same expressions in the same order, so the states after
 whole multirate steps must agree bit for bit; the kernel profile shows
@@ -38,7 +39,8 @@ def _run(kind, prim, dx, sch, nsteps, dt, fused):
 @pytest.mark.parametrize("kind,shape,sch,nsteps", [
     ("mech9", (7, 9, 70), (4, 3, 5, 1), 2),     # GL4 / GL5 type (b); x tile plus a ragged tail
     ("mech9le", (12, 10, 6), (4, 2, 3, 2), 1),  # GL3 repeated twice per coarse interval (type c)
-    ("mech21", (5, 6, 9), (4, 2, 5, 1), 1),     # 21 species: the two-kernel form either way
+    ("mech21", (5, 6, 9), (4, 2, 5, 1), 1),     # 21 species: the paired-lane one-kernel form
+    ("mech21", (6, 5, 7), (4, 2, 3, 2), 1),     # 21 species, GL3 twice per interval (type c)
     ("mech9", (6, 5, 7), (3, 2, 5, 1), 1),      # three coarse nodes: the two-kernel form either way
 ])
 def test_fused_fine_equals_two_kernel_form(kind, shape, sch, nsteps):
@@ -48,7 +50,7 @@ def test_fused_fine_equals_two_kernel_form(kind, shape, sch, nsteps):
     dt = time_step("box16_sdc")
     Uf, pf = _run(kind, prim, 1e-4, s, nsteps, dt, True)
     Us, ps = _run(kind, prim, 1e-4, s, nsteps, dt, False)
-    applies = m["ns"] <= 9 and sch[0] == 4 and (sch[2] - 1) * sch[3] == 4
+    applies = sch[0] == 4 and (sch[2] - 1) * sch[3] == 4
     print(kind, shape, sch, "one-kernel form applies:", applies, {k: v[1] for k, v in pf.items()})
     assert ("mr_src" not in pf) == applies
     assert "mr_src" in ps and "mr_fine" in pf and "mr_fine" in ps
