@@ -561,7 +561,11 @@ void eval_rhs_g(const Ops *o, const LaunchCtx &l, FRef U, double *P, double *G, 
   // source) and the direction passes add to it; without, the x pass stores
   // into F (bit 8) and nothing clears it first
   const bool react = parts & RHS_REACT, ad = parts & RHS_AD;
-  o->prims(l, U, P, F, react ? 2 : (ad ? 0 : 1), warm ? 1 : 0);
+  // the direction passes form the mole fractions from Y and the mean
+  // molecular weight above nine species (narrow stencil, correction
+  // velocity); every other form reads the stored ones
+  const bool store_x = o->ns <= 9 || l.wide || l.ref_species >= 0;
+  o->prims(l, U, P, F, react ? 2 : (ad ? 0 : 1), warm ? 1 : 0, store_x ? 1 : 0);
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
   if (ad) {
     for (int d = 0; d < 3; ++d) o->dir(l, d, U, P, G, F, (parts & RHS_AD) | (d == 0 && !react ? 8u : 0u));
@@ -1675,7 +1679,7 @@ int rhs_vjp_g(sdc_context *c, Plan *p, const LaunchCtx &l, double *U, const doub
   double *P = W + L.P, *G = W + L.G;
   const FRef Uf{U, nullptr};
   o->ghost(l, Uf);
-  o->prims(l, Uf, P, FRef{nullptr, nullptr}, 0, 0);
+  o->prims(l, Uf, P, FRef{nullptr, nullptr}, 0, 0, 1);   // the transposes read X
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
   adj_fill0(l, W + L.Pb, (long long)(L.Ub - L.Pb) + (long long)p->totS * nU);
   const AdjBufs ab{W + L.Ub, W + L.Pb, W + L.Gb};

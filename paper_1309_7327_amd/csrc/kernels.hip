@@ -138,7 +138,7 @@ template <int NS, bool CHEM>
 __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
                                                TileShape ts, FRef Uref, double *__restrict__ Pbase,
-                                               FRef Fout, int out_mode, int warm,
+                                               FRef Fout, int out_mode, int warm, int store_x,
                                                const DevMech *__restrict__ m, int *err) {
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       P[(L::PY + k) * nS + s] = Y[k];
-      P[(L::PX + k) * nS + s] = Y[k] * Wbar * m->invW[k];
+      if (store_x) P[(L::PX + k) * nS + s] = Y[k] * Wbar * m->invW[k];
       P[(L::PH + k) * nS + s] = m->Rk[k] * T * h_RT(m, k, T, invT);
     }
     if (out_mode == 0) continue;
@@ -1835,15 +1835,15 @@ struct Launch {
                        c.itemsG, c.nG, U);
     prof_end(c.prof, K_GHOST, c.stream);
   }
-  static void prims(const LaunchCtx &c, FRef U, double *P, FRef F, int out_mode, int warm) {
+  static void prims(const LaunchCtx &c, FRef U, double *P, FRef F, int out_mode, int warm, int store_x) {
     prof_begin(c.prof, K_PRIMS, c.stream);
     const dim3 grid(grid_for(c.nS, c.cap)), block(c.tsS.tx * c.tsS.ty * c.tsS.tz);
     if (out_mode == 2)
       hipLaunchKernelGGL((k_prims<NS, true>), grid, block, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F,
-                         out_mode, warm, c.mech, c.err);
+                         out_mode, warm, store_x, c.mech, c.err);
     else
       hipLaunchKernelGGL((k_prims<NS, false>), grid, block, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F,
-                         out_mode, warm, c.mech, c.err);
+                         out_mode, warm, store_x, c.mech, c.err);
     prof_end(c.prof, K_PRIMS, c.stream);
   }
   static void vgrad(const LaunchCtx &c, const double *P, double *G) {
