@@ -15,6 +15,12 @@ text records kept under profiles/.
       `bench.py --calibrate-copy` issues first; writes
       traffic_<kernel>_<workload>.json per kernel kind and
       traffic_<workload>.md, stamped with the hash of the kernel sources.
+  python -m paper_1309_7327_amd.rocpd_summary sq PASS1_DB PASS2_DB TRACE_DB --title TEXT --command CMD ...
+      per-kernel SQ counters from two counter runs (the SQ_SET_1 and
+      SQ_SET_2 lists below) and a kernel trace of the same command:
+      instructions per wave, VALU busy share, share of wave time waiting,
+      waves per SIMD, vector-memory and LDS instructions per wave, LDS bank
+      conflicts per LDS active cycle (markdown, stdout)
 """
 import argparse
 import collections
@@ -114,6 +120,48 @@ def fp64_table(db):
     return sorted(rows, key=lambda r: -r[2] * r[1])
 
 
+SQ_SET_1 = ("SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+            "SQ_WAIT_ANY", "SQ_INSTS_VALU", "SQ_INSTS_LDS")
+SQ_SET_2 = ("SQ_INSTS_SALU", "SQ_INSTS_SMEM", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_WAVES",
+            "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_ANY", "SQ_INST_CYCLES_VMEM_RD")
+CLOCK_HZ = 2.4e9
+SIMDS = 1024
+
+
+def counter_means(db):
+    """{short kernel name: {counter: mean over dispatches of the per-dispatch total}}."""
+    con = sqlite3.connect(db)
+    acc = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(float)))
+    for name, cname, val, did in con.execute(
+            "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        acc[short_name(name)][cname][did] += val
+    return {k: {c: sum(d.values()) / len(d) for c, d in cs.items()} for k, cs in acc.items()}
+
+
+def sq_table(db1, db2, trace_db):
+    """Rows (kernel, avg ms, waves, VALU instr / wave, VALU busy, waiting,
+    waves per SIMD, VMEM rd instr / wave, LDS instr / wave, bank conflicts /
+    LDS active cycles), ordered by total trace time.  VALU busy counts every
+    VALU instruction at the 4-cycle FP64 rate (a lower bound); waiting is
+    SQ_WAIT_ANY / SQ_WAVE_CYCLES; waves per SIMD is SQ_WAVE_CYCLES x 4 over
+    the dispatch's SIMD-cycles."""
+    c1, c2 = counter_means(db1), counter_means(db2)
+    rows = []
+    for name, n, tot, avg, pct in kernel_table(trace_db):
+        a, b = c1.get(name), c2.get(name)
+        if not a or not b or not b.get("SQ_WAVES"):
+            continue
+        dur = avg * 1e-9
+        waves = b["SQ_WAVES"]
+        simd_cycles = dur * CLOCK_HZ * SIMDS
+        lds_act = a.get("SQ_ACTIVE_INST_LDS", 0.0)
+        rows.append((name, avg * 1e-6, waves, a["SQ_INSTS_VALU"] / waves,
+                     a["SQ_INSTS_VALU"] * 4.0 / simd_cycles, a["SQ_WAIT_ANY"] / a["SQ_WAVE_CYCLES"],
+                     a["SQ_WAVE_CYCLES"] * 4.0 / simd_cycles, b["SQ_INSTS_VMEM_RD"] / waves,
+                     a["SQ_INSTS_LDS"] / waves, b["SQ_LDS_BANK_CONFLICT"] / lds_act if lds_act else 0.0))
+    return rows
+
+
 def traffic(fetch_db, write_db, workload, out_dir, cmd_fetch, cmd_write):
     f = counters(fetch_db, "FETCH_SIZE")
     w = counters(write_db, "WRITE_SIZE")
@@ -170,6 +218,12 @@ def main():
     f.add_argument("db")
     f.add_argument("--title", default="FP64 instruction counts")
     f.add_argument("--command", default="")
+    q = sub.add_parser("sq")
+    q.add_argument("db1")
+    q.add_argument("db2")
+    q.add_argument("trace")
+    q.add_argument("--title", default="SQ counters")
+    q.add_argument("--command", action="append", default=[])
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -201,6 +255,22 @@ def main():
             print(f"| {k} | {n} | {dur * 1e-6:.3f} | {c[FP64_COUNTERS[0]]:.4g} | {c[FP64_COUNTERS[1]]:.4g} | "
                   f"{c[FP64_COUNTERS[2]]:.4g} | {c[FP64_COUNTERS[3]]:.4g} | {fl * 1e-9:.3f} | {rate * 1e-12:.2f} | "
                   f"{100.0 * rate / FP64_PEAK:.1f}% |")
+    elif a.cmd == "sq":
+        print(f"# {a.title}\n")
+        if a.command:
+            print("Commands (from the repository root; each pass its own run):\n\n```\n" + "\n".join(a.command)
+                  + "\n```\n")
+        print(f"Kernel sources hash {source_hash()}. Counters are chip-wide totals per dispatch, averaged over "
+              "the dispatches of each kernel; durations from the kernel trace. VALU busy = SQ_INSTS_VALU x 4 "
+              "cycles / (duration x 2.4 GHz x 1024 SIMDs), a lower bound; waiting = SQ_WAIT_ANY / "
+              "SQ_WAVE_CYCLES (share of resident wave time in s_waitcnt); waves per SIMD = SQ_WAVE_CYCLES x 4 / "
+              "(duration x 2.4 GHz x 1024).\n")
+        print("| kernel | avg ms | waves | VALU instr / wave | VALU busy | waiting | waves per SIMD "
+              "| VMEM rd instr / wave | LDS instr / wave | LDS bank-conflict / LDS active cycles |\n"
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
+        for r in sq_table(a.db1, a.db2, a.trace):
+            print(f"| {r[0]} | {r[1]:.3f} | {r[2]:.0f} | {r[3]:.0f} | {100 * r[4]:.0f}% | {100 * r[5]:.0f}% | "
+                  f"{r[6]:.2f} | {r[7]:.0f} | {r[8]:.0f} | {100 * r[9]:.0f}% |")
     else:
         traffic(a.fetch, a.write, a.workload, a.out_dir, a.command_fetch, a.command_write)
 
