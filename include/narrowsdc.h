@@ -307,8 +307,11 @@ const char *last_error_message(const sdc_context *ctx);
  * sdc_kernel_name: name of kernel kind `id` ("" if out of range).
  * sdc_set_tiles: force the tile shapes (threads x, y, z; product <= 256,
  *   interior product a multiple of 64) of the interior and stored index
- *   spaces (0 = automatic) and cap the number of workgroups per launch
- *   (0 = one per work item). */
+ *   spaces, each independently (all three extents 0 = automatic) and cap
+ *   the number of workgroups per launch (0 = one per work item); an extent
+ *   set that mixes zero and non-zero values, a negative value or a
+ *   negative cap returns SDC_EINVAL.  Forcing either shape bypasses the
+ *   autotuner's choice for later plans. */
 int sdc_profile_enable(sdc_context *ctx, int enable);
 int sdc_profile_read(sdc_context *ctx, void *stream, double *total_ms, int *count);
 const char *sdc_kernel_name(int id);

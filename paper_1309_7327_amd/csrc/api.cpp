@@ -375,25 +375,25 @@ void plan_shape(const sdc_context *c, int nbox, const box_desc *bx, TileShape &t
   // batches run as persistent launches: a few workgroups per compute unit
   // walk the (box, tile) list
   cap = nbox > 1 ? 4 * std::max(c->n_cu, 1) : 0;
-  auto tu = c->forceI.tx ? c->tuned.end() : c->tuned.find(box_signature(nbox, bx));
-  if (c->forceI.tx) {
-    tI = c->forceI;
-    tS = c->forceS;
-  } else if (tu != c->tuned.end()) {
+  const bool forced = c->forceI.tx || c->forceS.tx;
+  auto tu = forced ? c->tuned.end() : c->tuned.find(box_signature(nbox, bx));
+  if (tu != c->tuned.end()) {
     tI = tu->second.tI;
     tS = tu->second.tS;
     cap = tu->second.cap;
-  } else {
-    int mx = 0, my = 0, mz = 0;
-    for (int i = 0; i < nbox; ++i) {
-      mx = std::max(mx, bx[i].nx);
-      my = std::max(my, bx[i].ny);
-      mz = std::max(mz, bx[i].nz);
-    }
-    if (nbox > 1) mx = 16;   // batches: one tile shape for every box
-    tI = default_tile(mx, my, mz);
-    tS = default_tile(nbox > 1 ? 16 : mx + 8, my + 8, mz + 8);
+    return;
   }
+  int mx = 0, my = 0, mz = 0;
+  for (int i = 0; i < nbox; ++i) {
+    mx = std::max(mx, bx[i].nx);
+    my = std::max(my, bx[i].ny);
+    mz = std::max(mz, bx[i].nz);
+  }
+  if (nbox > 1) mx = 16;   // batches: one tile shape for every box
+  // a shape forced by sdc_set_tiles replaces the default; a zero shape
+  // leaves its index space automatic
+  tI = c->forceI.tx ? c->forceI : default_tile(mx, my, mz);
+  tS = c->forceS.tx ? c->forceS : default_tile(nbox > 1 ? 16 : mx + 8, my + 8, mz + 8);
 }
 
 // Host side of a work plan for p->boxes with p's tile shapes: the per-box
@@ -1588,8 +1588,11 @@ const char *last_error_message(const sdc_context *c) { return c ? c->msg.c_str()
 // grid size of every launch (0 = one workgroup per item).
 int sdc_set_tiles(sdc_context *c, int ix, int iy, int iz, int sx, int sy, int sz, int grid_cap) {
   if (!c) return SDC_EINVAL;
-  if (ix * iy * iz > 256 || sx * sy * sz > 256 || ix < 0 || sx < 0)
-    return fail(c, SDC_EINVAL, "tile larger than 256 threads");
+  // each shape is all zero (automatic) or all positive
+  auto valid = [](int x, int y, int z) { return (x == 0 && y == 0 && z == 0) || (x > 0 && y > 0 && z > 0); };
+  if (!valid(ix, iy, iz) || !valid(sx, sy, sz) || grid_cap < 0)
+    return fail(c, SDC_EINVAL, "tile extents must be all zero or all positive, grid_cap >= 0");
+  if (ix * iy * iz > 256 || sx * sy * sz > 256) return fail(c, SDC_EINVAL, "tile larger than 256 threads");
   if ((ix * iy * iz) % 64 != 0) return fail(c, SDC_EINVAL, "interior tile must be a multiple of 64 threads");
   c->forceI = TileShape{ix, iy, iz};
   c->forceS = TileShape{sx, sy, sz};

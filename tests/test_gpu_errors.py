@@ -86,6 +86,11 @@ def test_bad_arguments_are_einval(good):
     bad_sch = N.scheme(1, 2, 0, 1)
     assert L.sdc_step(ctx.h, ctypes.byref(bx), _ptr(U), 1e-9, 1, ctypes.byref(bad_sch), _ptr(ws), nb,
                       s) == N.SDC_EINVAL
+    # tile shapes: each all zero (automatic) or all positive, at most 256
+    # threads, the interior one whole waves
+    for bad in ((64, 0, 1, 0, 0, 0, 0), (0, 0, 0, 16, 0, 16, 0), (64, 4, -1, 0, 0, 0, 0),
+                (64, 8, 1, 0, 0, 0, 0), (32, 3, 1, 0, 0, 0, 0), (0, 0, 0, 0, 0, 0, -1)):
+        assert L.sdc_set_tiles(ctx.h, *bad) == N.SDC_EINVAL
     # nothing was launched by the rejected calls: the state is intact
     ctx.check_status()
 

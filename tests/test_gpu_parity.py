@@ -70,8 +70,9 @@ def test_rhs_eval_deterministic_and_tile_independent():
     prim = fields.sines(shape, 1e-4, m["ns"], 5)
     bx, U = G.device_state(ctx, prim, 1e-4)
     outs = []
+    # (one index space forced and the other automatic, both ways round)
     for tiles in [((0, 0, 0), (0, 0, 0)), ((16, 4, 4), (16, 4, 4)), ((64, 2, 2), (8, 8, 4)),
-                  ((8, 8, 2), (32, 8, 1))]:
+                  ((8, 8, 2), (32, 8, 1)), ((32, 8, 1), (0, 0, 0)), ((0, 0, 0), (16, 8, 2))]:
         ctx.set_tiles(*tiles, grid_cap=37)
         for _ in range(2):
             F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
