@@ -83,7 +83,8 @@ typedef struct {
  * rho D_k = lambda / (c_p Le_k), bulk viscosity xi = bulk_ratio * mu.
  * m47, m48: the two free parameters of the eighth-order narrow stencil. */
 typedef struct {
-  int ns, nr;            /* species (9 or 21 supported), reactions (<= 256) */
+  int ns, nr;            /* species (a count the library was built for, see
+                            sdc_species_supported), reactions (<= 256) */
   const double *W;       /* [ns] molecular weights, kg/mol */
   const double *nasa;    /* [ns][7] */
   double Tlo, Thi;
@@ -127,6 +128,12 @@ int sdc_context_destroy(sdc_context *ctx);
 /* Copy a mechanism to the device (synchronous).  Returns SDC_EINVAL for
  * unsupported sizes or reactions with more than two molecules per side. */
 int set_mechanism(sdc_context *ctx, const mechanism_desc *mech);
+
+/* 1 if the kernels were compiled for `ns` species, else 0 (no device call).
+ * Every kernel is specialised for its species count, as a code generated
+ * for one mechanism is; the default build covers 9, 12 and 21 species, and
+ * the build's NSDC_SPECIES_COUNTS list (counts 1..24) sets others. */
+int sdc_species_supported(int ns);
 
 /* Conserved state from primitives on the interior: p, T [nz][ny][nx],
  * Y [ns][nz][ny][nx], u [3][nz][ny][nx] (device, interior layout) -> U

@@ -943,15 +943,16 @@ static const AdjOps make_adj_ops() {
   o.fold = &AdjLaunch<NS>::fold;
   return o;
 }
-static const AdjOps ADJ9 = make_adj_ops<9>();
-static const AdjOps ADJ21 = make_adj_ops<21>();
+#define NSDC_ADJ_DEF(n) static const AdjOps ADJ_##n = make_adj_ops<n>();
+NSDC_SPECIES_COUNTS(NSDC_ADJ_DEF)
+#undef NSDC_ADJ_DEF
 
 const AdjOps *adj_ops_for(int ns) {
-  switch (ns) {
-    case 9: return &ADJ9;
-    case 21: return &ADJ21;
-    default: return nullptr;
-  }
+#define NSDC_ADJ_CASE(n) \
+  if (ns == (n)) return &ADJ_##n;
+  NSDC_SPECIES_COUNTS(NSDC_ADJ_CASE)
+#undef NSDC_ADJ_CASE
+  return nullptr;
 }
 
 }  // namespace nsdc

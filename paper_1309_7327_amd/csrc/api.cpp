@@ -1139,10 +1139,17 @@ int sdc_context_destroy(sdc_context *c) {
   return SDC_OK;
 }
 
+int sdc_species_supported(int ns) { return ops_for(ns) ? 1 : 0; }
+
 int set_mechanism(sdc_context *c, const mechanism_desc *m) {
   if (!c || !m) return fail(c, SDC_EINVAL, "null argument");
   const Ops *o = ops_for(m->ns);
-  if (!o) return fail(c, SDC_EINVAL, "unsupported species count (9 or 21)");
+  if (!o) {
+#define NSDC_COUNT_STR(n) " " #n
+    return fail(c, SDC_EINVAL, "species count not among those the library was built for:" NSDC_SPECIES_COUNTS(
+                                   NSDC_COUNT_STR));
+#undef NSDC_COUNT_STR
+  }
   if (m->nr < 0 || m->nr > NSDC_NRMAX) return fail(c, SDC_EINVAL, "too many reactions");
   if (!m->W || !m->nasa || !m->Le || (m->nr > 0 && (!m->A || !m->b || !m->Ea || !m->nu_f || !m->nu_r)))
     return fail(c, SDC_EINVAL, "null mechanism array");

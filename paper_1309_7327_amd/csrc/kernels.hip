@@ -2006,14 +2006,17 @@ static const Ops make_ops() {
   o.mr2_node = &Launch<NS>::mr2_node;
   return o;
 }
-static const Ops OPS9 = make_ops<9>();
-static const Ops OPS21 = make_ops<21>();
+#define NSDC_OPS_DEF(n)                                                  \
+  static_assert((n) >= 1 && (n) <= NSDC_NSMAX, "species count out of range"); \
+  static const Ops OPS_##n = make_ops<n>();
+NSDC_SPECIES_COUNTS(NSDC_OPS_DEF)
+#undef NSDC_OPS_DEF
 
 const Ops *ops_for(int ns) {
-  switch (ns) {
-    case 9: return &OPS9;
-    case 21: return &OPS21;
-    default: return nullptr;
-  }
+#define NSDC_OPS_CASE(n) \
+  if (ns == (n)) return &OPS_##n;
+  NSDC_SPECIES_COUNTS(NSDC_OPS_CASE)
+#undef NSDC_OPS_CASE
+  return nullptr;
 }
 }  // namespace nsdc

@@ -5,6 +5,15 @@
 
 #define NSDC_NG 4
 #define NSDC_NSMAX 24
+
+// Species counts the kernels are compiled for (each an instantiation of
+// every kernel template, as a code generated for one mechanism would be);
+// a build may pass its own list, e.g.
+//   -D'NSDC_SPECIES_COUNTS(X)=X(9) X(15) X(21)'
+// with every count in [1, NSDC_NSMAX].
+#ifndef NSDC_SPECIES_COUNTS
+#define NSDC_SPECIES_COUNTS(X) X(9) X(12) X(21)
+#endif
 #define NSDC_NRMAX 256
 #define NSDC_MAXNODES 40
 #define NSDC_MAXFINE 33

@@ -50,6 +50,7 @@ _SIGS = {
     "sdc_context_create": [ctypes.POINTER(_vp), _ip],
     "sdc_context_destroy": [_vp],
     "set_mechanism": [_vp, ctypes.POINTER(MechanismDesc)],
+    "sdc_species_supported": [_ip],
     "prim_to_cons": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, _vp, _vp, _vp, _vp],
     "rhs_eval": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, ctypes.c_uint, _vp],
     "rhs_eval_static": [_vp, ctypes.POINTER(BoxDesc), _vp, _vp, ctypes.c_uint, _vp],
@@ -102,6 +103,11 @@ def box(nx, ny, nz, dx, dy=None, dz=None, nonperiodic=0):
 
 def scheme(n_coarse=4, sweeps=6, n_fine=0, fine_repeat=1, mode=1):
     return Scheme(n_coarse, sweeps, n_fine, fine_repeat, mode)
+
+
+def species_supported(ns):
+    """Whether the library's kernels were compiled for ``ns`` species."""
+    return bool(_lib.sdc_species_supported(int(ns)))
 
 
 def _stream(stream):

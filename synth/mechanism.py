@@ -181,9 +181,40 @@ MANIFEST_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__fi
 
 def load(kind):
     """Mechanism ``kind`` from its stored reaction selection."""
+    if kind in SUBSETS:
+        base, names = SUBSETS[kind]
+        return subset(load(base), names, kind)
     with open(os.path.join(MANIFEST_DIR, f"{kind}.json")) as f:
         sel = json.load(f)
     return assemble(kind, sel["seed"], [tuple(c) for c in sel["chosen"]])
+
+
+# mechanisms that keep a subset of another's species and the reactions among
+# them (element balance and the screening carry over): a CO/H2/O2-shaped
+# 12-species set from the 21-species mechanism
+SUBSETS = {
+    "mech12": ("mech21", ["H2", "O2", "H", "O", "OH", "H2O", "HO2", "H2O2", "CO", "CO2", "HCO", "N2"]),
+}
+
+
+def subset(m, names, kind):
+    """Mechanism ``m`` restricted to the species ``names`` (in that order)
+    and to the reactions whose reactants and products are all among them."""
+    idx = [m["species"].index(s) for s in names]
+    keep = np.zeros(m["ns"], bool)
+    keep[idx] = True
+    rows = [j for j in range(m["nr"]) if not ((m["nu_f"][j] > 0) | (m["nu_r"][j] > 0))[~keep].any()]
+    out = dict(m)
+    out.update(
+        kind=kind, species=list(names), ns=len(idx), nr=len(rows),
+        W=np.asarray(m["W"])[idx], nasa=np.asarray(m["nasa"])[idx], Le=np.asarray(m["Le"])[idx],
+        A=np.asarray(m["A"])[rows], b=np.asarray(m["b"])[rows], Ea=np.asarray(m["Ea"])[rows],
+        nu_f=np.ascontiguousarray(np.asarray(m["nu_f"])[rows][:, idx]),
+        nu_r=np.ascontiguousarray(np.asarray(m["nu_r"])[rows][:, idx]),
+        composition=np.asarray(m["composition"])[idx],
+        chosen=[m["chosen"][j] for j in rows],
+    )
+    return out
 
 
 def small_test_mechanism(seed=5, ns_keep=None):

@@ -63,7 +63,8 @@ def gpu_vjp(ctx, m, bx, Ug, v, parts=N.RHS_ALL):
 
 @pytest.mark.parametrize("kind,shape,parts", [
     ("mech9", (5, 6, 7), N.RHS_HYP), ("mech9", (5, 6, 7), N.RHS_DIFF), ("mech9", (5, 6, 7), N.RHS_REACT),
-    ("mech9", (5, 6, 7), N.RHS_ALL), ("mech9le", (6, 5, 4), N.RHS_ALL), ("mech21", (4, 5, 6), N.RHS_ALL)])
+    ("mech9", (5, 6, 7), N.RHS_ALL), ("mech9le", (6, 5, 4), N.RHS_ALL), ("mech21", (4, 5, 6), N.RHS_ALL),
+    ("mech12", (5, 4, 6), N.RHS_ALL)])
 def test_rhs_vjp_matches_oracle_on_small_boxes(kind, shape, parts):
     """Every entry of (d rhs/dU)^T v against the oracle's column-by-column
     definition; boxes smaller than the stencil, so lines wrap onto

@@ -42,6 +42,7 @@ def _run(kind, prim, dx, sch, nsteps, dt, fused):
     ("mech21", (5, 6, 9), (4, 2, 5, 1), 1),     # 21 species: the paired-lane one-kernel form
     ("mech21", (6, 5, 7), (4, 2, 3, 2), 1),     # 21 species, GL3 twice per interval (type c)
     ("mech9", (6, 5, 7), (3, 2, 5, 1), 1),      # three coarse nodes: the two-kernel form either way
+    ("mech12", (6, 7, 5), (4, 2, 5, 1), 1),     # 12 species: six per lane of a pair
 ])
 def test_fused_fine_equals_two_kernel_form(kind, shape, sch, nsteps):
     m = mechanism.load(kind)

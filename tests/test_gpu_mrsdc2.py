@@ -46,6 +46,7 @@ def oracle_mode2(om, dx, V, dt, nc, nf, rep, K, nsteps, pt=None):
     ("mech9", (6, 7, 5), (4, 3, 5, 1), 1, 1.0),       # GL4 coarse, GL5 fine (type b)
     ("mech9le", (6, 5, 7), (3, 3, 3, 2), 1, 8.0),     # a step 8x the explicit workload's
     ("mech21", (5, 6, 7), (3, 2, 3, 1), 1, 1.0),      # 21 species
+    ("mech12", (6, 5, 5), (3, 2, 3, 1), 1, 1.0),      # 12 species
 ])
 def test_mode2_step_parity(kind, shape, sch, nsteps, dtmul):
     m, om, ctx = mech(kind)

@@ -30,7 +30,8 @@ def mech(kind):
 
 
 @pytest.mark.parametrize("kind,shape", [("mech9", (16, 16, 16)), ("mech9le", (5, 6, 7)),
-                                        ("mech21", (9, 12, 20)), ("mech9", (24, 20, 36))])
+                                        ("mech21", (9, 12, 20)), ("mech9", (24, 20, 36)),
+                                        ("mech12", (7, 10, 13))])
 def test_prim_to_cons(kind, shape):
     m, om, ctx = mech(kind)
     prim = fields.sines(shape, 1e-4, m["ns"], 7)
@@ -50,6 +51,7 @@ def test_prim_to_cons(kind, shape):
     ("mech9le", (5, 6, 7), (1e-4, 1.2e-4, 0.9e-4)),   # ragged, anisotropic, V_c and bulk active
     ("mech21", (9, 12, 20), 1e-4),
     ("mech9", (24, 20, 36), 1e-4),            # several tiles with ragged tails
+    ("mech12", (7, 10, 13), 1e-4),            # a third species count of the build
 ])
 def test_rhs_eval_parity(kind, shape, dx, parts):
     m, om, ctx = mech(kind)
@@ -106,6 +108,7 @@ def _run_gpu_sdc(ctx, bx, U, dt, sch, nsteps):
     ("mech9le", (6, 5, 7), dict(n_coarse=3, sweeps=4, n_fine=0), 3),
     ("mech9", (8, 8, 8), dict(n_coarse=4, sweeps=6, n_fine=5, fine_repeat=1), 2),  # MRSDC type (b)
     ("mech21", (6, 8, 5), dict(n_coarse=3, sweeps=4, n_fine=3, fine_repeat=2), 1),  # MRSDC type (c)
+    ("mech12", (6, 5, 9), dict(n_coarse=4, sweeps=3, n_fine=5, fine_repeat=1), 1),  # 12 species, one kernel
 ])
 def test_sdc_step_parity(kind, shape, sch, nsteps):
     m, om, ctx = mech(kind)

@@ -49,3 +49,12 @@ def test_binding_fails_loudly_without_library(tmp_path):
     r = subprocess.run([sys.executable, "-c", "import sys; sys.path.insert(0, %r); import paper_1309_7327_amd.narrowsdc" % str(tmp_path)],
                        capture_output=True, text=True, env=env)
     assert r.returncode != 0 and "no CPU fallback" in r.stderr
+
+
+def test_species_counts_of_the_build():
+    """The kernels are specialised per species count; the query touches no
+    device.  The default build covers 9, 12 and 21 species."""
+    lib = ctypes.CDLL(LIB)
+    lib.sdc_species_supported.argtypes = [ctypes.c_int]
+    lib.sdc_species_supported.restype = ctypes.c_int
+    assert [n for n in range(0, 30) if lib.sdc_species_supported(n)] == [9, 12, 21]

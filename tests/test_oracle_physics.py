@@ -11,7 +11,7 @@ RU = 8.31446261815324
 
 @pytest.fixture(scope="module")
 def mechs(orc):
-    return {k: orc.Mechanism(mechanism.load(k)) for k in ("mech9", "mech9le", "mech21")}
+    return {k: orc.Mechanism(mechanism.load(k)) for k in ("mech9", "mech9le", "mech12", "mech21")}
 
 
 def _state(orc, om, shape=(8, 8, 8), seed=3):
@@ -351,3 +351,27 @@ def test_wide_stencil_does_not_see_the_nyquist_mode(orc, mechs):
     fn = orc.rhs(om, U, 1e-4, parts=orc.DIFF)
     assert np.abs(fn[4]).max() > 1e6
     assert np.abs(fw[4]).max() <= 1e-9 * np.abs(fn[4]).max()
+
+
+def test_subset_mechanism_keeps_its_parents_data():
+    """The 12-species mechanism is the 21-species one restricted to a species
+    subset: every kept reaction appears in the parent with the same species
+    (mapped by name) and the same Arrhenius triple, every parent reaction
+    among the kept species is kept, and each reaction balances elements."""
+    full, sub = mechanism.load("mech21"), mechanism.load("mech12")
+    pos = [full["species"].index(s) for s in sub["species"]]
+    parent = {}
+    for j in range(full["nr"]):
+        parent[(tuple(full["nu_f"][j]), tuple(full["nu_r"][j]))] = (full["A"][j], full["b"][j], full["Ea"][j])
+    inside = 0
+    for j in range(full["nr"]):
+        used = (full["nu_f"][j] > 0) | (full["nu_r"][j] > 0)
+        inside += all(used[k] == 0 or k in pos for k in range(full["ns"]))
+    assert sub["nr"] == inside > 0
+    for j in range(sub["nr"]):
+        nf, nr_ = np.zeros(full["ns"], np.int32), np.zeros(full["ns"], np.int32)
+        nf[pos], nr_[pos] = sub["nu_f"][j], sub["nu_r"][j]
+        assert parent[(tuple(nf), tuple(nr_))] == (sub["A"][j], sub["b"][j], sub["Ea"][j])
+        assert not ((sub["nu_r"][j] - sub["nu_f"][j]) @ sub["composition"]).any()
+    np.testing.assert_array_equal(sub["W"], np.asarray(full["W"])[pos])
+    np.testing.assert_array_equal(sub["nasa"], np.asarray(full["nasa"])[pos])
