@@ -30,7 +30,8 @@ def build(verbose=False):
     with ThreadPoolExecutor(len(cmds)) as ex:
         list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
-    run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
+        ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)

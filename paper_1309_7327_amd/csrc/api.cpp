@@ -15,6 +15,7 @@
 #include "../../include/narrowsdc.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstring>
@@ -318,6 +319,15 @@ constexpr size_t STAGE_BYTES = size_t(1) << 20;
 }  // namespace
 
 namespace {
+
+// A roctx range over a host scope: rocprofv3 --marker-trace shows the
+// library's calls, steps and sweeps around the kernels they enqueue.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
 
 int fail(sdc_context *c, int code, const std::string &m) {
   if (c) c->msg = m;
@@ -749,6 +759,7 @@ int run_mrsdc2(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const
     for (int j = 0; j <= M1; ++j) F1old[j] = s10;
     for (int q = 0; q <= M2; ++q) F2old[q] = s20;
     for (int k = 0; k < K; ++k) {
+      const Range sweep_range("sweep");
       F1new[0] = s10;
       F2new[0] = s20;
       for (int m = 1; m <= M1; ++m) F1new[m] = (k % 2 == 0) ? s1A[m] : s1B[m];
@@ -871,6 +882,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
       double rprev = -1.0;
       int kdone = K;
       for (int k = 0; k < K; ++k) {
+        const Range sweep_range("sweep");
         Fnew[0] = F0;
         for (int m = 1; m <= M; ++m) Fnew[m] = (k % 2 == 0) ? FA[m] : FB[m];
         FRef Ucur = Uuser;
@@ -959,6 +971,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
     for (int j = 0; j <= M; ++j) F1old[j] = s10;
     for (int q = 0; q <= M2; ++q) F2old[q] = s20;
     for (int k = 0; k < K; ++k) {
+      const Range sweep_range("sweep");
       F1new[0] = s10;
       F2new[0] = s20;
       for (int m = 1; m <= M; ++m) F1new[m] = (k % 2 == 0) ? s1A[m] : s1B[m];
@@ -1289,6 +1302,7 @@ int rhs_eval(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsig
   }
   double *P = c->scratch;
   double *G = P + ((((size_t)pl->totS * (9 + 3 * ns)) + 31) & ~size_t(31));
+  const Range range("rhs_eval");
   const LaunchCtx l = make_lc(c, pl, (hipStream_t)stream);
   eval_rhs_g(c->ops, l, FRef{U, nullptr}, P, G, FRef{dUdt, nullptr}, parts);
   HIPCHECK(c, hipGetLastError());
@@ -1368,6 +1382,7 @@ namespace {
 int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U, double dt,
                int nsteps, const sdc_scheme *scheme, void *workspace, size_t ws_bytes,
                hipStream_t stream) {
+  const Range range(nbox > 1 ? "sdc_step_batched" : "sdc_step");
   c->resid_hist.clear();
   c->last_sweeps = 0;
   if (c->resid_ratio > 0.0 && (nbox > 1 || scheme->n_fine != 0))
@@ -1896,6 +1911,7 @@ int rhs_vjp(sdc_context *c, const box_desc *box, double *U, const double *dUdt_b
   if (rc) return rc;
   if (!U || !dUdt_bar || !U_bar) return fail(c, SDC_EINVAL, "null field pointer");
   if (parts == 0 || (parts & ~7u)) return fail(c, SDC_EINVAL, "bad parts mask");
+  const Range range("rhs_vjp");
   HIPCHECK(c, hipSetDevice(c->device));
   Plan *pl;
   rc = get_plan(c, 1, box, nullptr, &pl);
@@ -1965,6 +1981,7 @@ int sdc_step_vjp(sdc_context *c, const box_desc *box, double *U0, double dt, int
   if (scheme->n_fine != 0) return fail(c, SDC_EINVAL, "the adjoint supports single-rate SDC (n_fine = 0)");
   if (!U0 || !UN_bar || !U0_bar) return fail(c, SDC_EINVAL, "null field pointer");
   if (nsteps < 1 || !(dt > 0)) return fail(c, SDC_EINVAL, "nsteps >= 1 and dt > 0 required");
+  const Range range("sdc_step_vjp");
   HIPCHECK(c, hipSetDevice(c->device));
   Plan *pl;
   rc = get_plan(c, 1, box, nullptr, &pl);
