@@ -1584,9 +1584,13 @@ struct Mr2Slot {
 };
 static_assert(Mr2Slot<21>::W + 22 == NSDC_MR2_SLOT(21), "mode-2 slot layout");
 
-template <int NS>
+// LANES = 2: the two lanes of a cell (32 apart in one wave) share its slot
+// in LDS; both write the same per-species values and form the same matrix
+// (identical writes), each takes every other reaction and adds its terms
+// with LDS atomics (a wave executes them in a fixed lane order).
+template <int NS, int LANES = 1>
 __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<NS> &sl, const double *y,
-                                   double rho, double T, double cv, double h) {
+                                   double rho, double T, double cv, double h, int sub = 0) {
   const double lnT = log(T), invT = 1.0 / T;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -1605,7 +1609,14 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
   sl(sl.W + NS) = 0.0;
   const double lnRTp = lnT + LN_RU_PREF;
   const int nr = m->nr;
-  for (int j = 0; j < nr; ++j) {
+  auto add = [&](double &dst, double v) {
+    if constexpr (LANES == 1)
+      dst += v;
+    else
+      atomicAdd(&dst, v);
+  };
+  if constexpr (LANES > 1) wave_sync();
+  for (int j = sub; j < nr; j += LANES) {
     const int sp[4] = {m->rs[j][0], m->rs[j][1], m->ps[j][0], m->ps[j][1]};
     const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
     const double dg = (sl(sl.GR + sp[2]) + sl(sl.GR + sp[3])) - (sl(sl.GR + sp[0]) + sl(sl.GR + sp[1]));
@@ -1625,14 +1636,15 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
     for (int i = 0; i < 4; ++i) {
       const double sgn = i < 2 ? -1.0 : 1.0;
       const int k = sp[i];
-      sl(sl.W + k) += sgn * q;
-      sl(sl.AT + k) += sgn * dqdT;
+      add(sl(sl.W + k), sgn * q);
+      add(sl(sl.AT + k), sgn * dqdT);
       if (k < NS)
 #pragma unroll
         for (int l = 0; l < 4; ++l)
-          if (sp[l] < NS) sl.a(k, sp[l]) += sgn * dq[l] * m->invW[sp[l]];
+          if (sp[l] < NS) add(sl.a(k, sp[l]), sgn * dq[l] * m->invW[sp[l]]);
     }
   }
+  if constexpr (LANES > 1) wave_sync();
   // A = I - h W_k (d(sum nu q)/dy_m + aT_k dT/dy_m); w_k = W_k (sum nu q)_k
   const double irc = 1.0 / (rho * cv);
   double dTdy[NS];
@@ -1700,23 +1712,27 @@ __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
 // LDS: up to 9 species, the slots in LDS, one wave per workgroup making as
 // many passes over the interior tile as it has waves of cells; otherwise the
 // workspace slots, one lane per cell of the tile.
-template <int NS, bool LDS>
+template <int NS, bool LDS, int LANES = 1>
 __global__ __launch_bounds__(LDS ? 64 : 256) void k_mr2_imp(const BoxDev *__restrict__ boxes,
                                                             const Item *__restrict__ items, int nitems,
                                                             TileShape ts, FRef Ucur, Mr2Imp a,
                                                             const DevMech *__restrict__ m, int *err) {
   constexpr int NU = 5 + NS;
-  __shared__ double slot_sh[LDS ? NSDC_MR2_SLOT(NS) * 64 : 1];
-  const Mr2Slot<NS> sl = LDS ? Mr2Slot<NS>{slot_sh + threadIdx.x, 64}
+  // LDS: CPP cells per pass, the LANES lanes of a cell CPP apart
+  constexpr int CPP = 64 / LANES;
+  static_assert(LANES == 1 || LDS, "lanes share a slot in LDS only");
+  __shared__ double slot_sh[LDS ? NSDC_MR2_SLOT(NS) * CPP : 1];
+  const int sub = LANES > 1 ? (int)threadIdx.x / CPP : 0, cslot = (int)threadIdx.x % CPP;
+  const Mr2Slot<NS> sl = LDS ? Mr2Slot<NS>{slot_sh + cslot, CPP}
                              : Mr2Slot<NS>{a.J + (long long)blockIdx.x * blockDim.x + threadIdx.x, a.jstride};
   const int tcells = ts.tx * ts.ty * ts.tz;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
-    for (int pass = 0; pass < (LDS ? (tcells + 63) / 64 : 1); ++pass) {
+    for (int pass = 0; pass < (LDS ? (tcells + CPP - 1) / CPP : 1); ++pass) {
       int x, y, z;
       if constexpr (LDS) {
-        const int lin = pass * 64 + (int)threadIdx.x;
+        const int lin = pass * CPP + cslot;
         if (lin >= tcells) continue;
         x = w.x0 + lin % ts.tx;
         y = w.y0 + (lin / ts.tx) % ts.ty;
@@ -1756,7 +1772,7 @@ __global__ __launch_bounds__(LDS ? 64 : 256) void k_mr2_imp(const BoxDev *__rest
         double cv = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
-        mr2_rates_jacobian<NS>(m, sl, yv, rho, T, cv, a.h);
+        mr2_rates_jacobian<NS, LANES>(m, sl, yv, rho, T, cv, a.h, sub);
 #pragma unroll
         for (int k = 0; k < NS; ++k) sl(sl.G + k) = yv[k] - a.h * sl(sl.W + k) - bv[k];
         mr2_solve<NS>(sl);
@@ -1777,9 +1793,10 @@ __global__ __launch_bounds__(LDS ? 64 : 256) void k_mr2_imp(const BoxDev *__rest
       double cv = 0.0;
 #pragma unroll
       for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
-      mr2_rates_jacobian<NS>(m, sl, yv, rho, T, cv, a.h);
+      mr2_rates_jacobian<NS, LANES>(m, sl, yv, rho, T, cv, a.h, sub);
 #pragma unroll
-      for (int k = 0; k < NS; ++k) a.X[o1 + k * nI] = sl(sl.W + k);
+      for (int k = 0; k < NS; ++k)
+        if (LANES == 1 || k % LANES == sub) a.X[o1 + k * nI] = sl(sl.W + k);
       if (errs) atomicOr(err, errs);
     }
   }
@@ -1926,6 +1943,11 @@ struct Launch {
     if constexpr (NS <= 9) {
       // the Newton matrices in LDS: one wave per workgroup
       hipLaunchKernelGGL((k_mr2_imp<NS, true>), dim3(grid_for(c.nI, c.cap)), dim3(64), 0, c.stream, c.boxes,
+                         c.itemsI, c.nI, c.tsI, Ucur, a, c.mech, c.err);
+    } else if constexpr (NS <= 12) {
+      // two lanes per cell sharing its slot in LDS (one lane's slot would
+      // leave one workgroup per compute unit)
+      hipLaunchKernelGGL((k_mr2_imp<NS, true, 2>), dim3(grid_for(c.nI, c.cap)), dim3(64), 0, c.stream, c.boxes,
                          c.itemsI, c.nI, c.tsI, Ucur, a, c.mech, c.err);
     } else {
       // the lanes' workspace slots bound the grid (the workspace holds
