@@ -17,8 +17,9 @@ timed region of exactly K steps; the line also carries Mcell
 advection-diffusion and reaction evaluations per second, the roofline of the
 dominant kernel and of the three stencil direction passes together (average
 durations from HIP events recorded on the launch stream around every launch
-of the timed region), the same K steps timed again with no events attached
-(unprofiled_ms_per_step), and the oracle baseline.
+of the timed region), the same K steps timed three more times with no
+events attached (their per-step median: unprofiled_ms_per_step), and the
+oracle baseline.
 """
 import argparse
 import json
@@ -442,12 +443,15 @@ def run_box(args, workload, steps, warmup, with_baseline):
     nk = lib.sdc_profile_read(ctx.h, ctypes.c_void_p(stream.cuda_stream), tot, cnt)
     kern = {lib.sdc_kernel_name(i).decode(): (tot[i], cnt[i]) for i in range(nk) if cnt[i] > 0}
     lib.sdc_profile_enable(ctx.h, 0)
-    # the same number of steps with no events attached
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ctx.sdc_step(bx, U, dt, steps, sch, ws, nb)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
+    # the same number of steps with no events attached, three times (their
+    # median per step beside the timed region's figure)
+    reps = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ctx.sdc_step(bx, U, dt, steps, sch, ws, nb)
+        torch.cuda.synchronize()
+        reps.append(1e3 * (time.perf_counter() - t2) / steps)
     ctx.check_status()
 
     el = t1 - t0
@@ -489,7 +493,8 @@ def run_box(args, workload, steps, warmup, with_baseline):
     out = {
         "value": steps_per_s,
         "ms_per_step": 1e3 * el / steps,
-        "unprofiled_ms_per_step": 1e3 * (t3 - t2) / steps,
+        "unprofiled_ms_per_step": float(np.median(reps)),
+        "unprofiled_ms_per_step_repeats": [round(v, 4) for v in reps],
         "config": {"workload": workload, "cells": ncell, "species": ns, "reactions": int(mech["nr"]),
                    "scheme": sch_d, "dt": dt,
                    "second_derivatives": "wide stencil D(a D u)" if wl.get("wide") else "narrow stencil",
