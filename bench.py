@@ -38,9 +38,10 @@ FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 # or logarithm counts 25 flops.
 def work_model(ns, nr, n_coarse, n_fine_per_interval, fused=False):
     nu = 5 + ns
-    # primitive fields per cell: u, T, p, mu, lambda, rho D, Y, h and the mean
-    # molecular weight (the mole fractions follow from Y and it)
-    np_ = 9 + 2 * ns
+    # primitive fields per cell: u, T, p, mu, lambda, rho D, the mean molecular
+    # weight and Y (the mole fractions follow from Y and the mean molecular
+    # weight, the species enthalpies from T)
+    np_ = 9 + ns
     # one direction of the stencil pass: convective divergence, narrow row sums
     # shared per field and face pairs, first derivatives of the mixed and
     # correction-velocity terms

@@ -572,8 +572,9 @@ void eval_rhs_g(const Ops *o, const LaunchCtx &l, FRef U, double *P, double *G, 
   // into F (bit 8) and nothing clears it first
   const bool react = parts & RHS_REACT, ad = parts & RHS_AD;
   // the direction passes form the mole fractions from Y and the mean
-  // molecular weight above nine species (narrow stencil, correction
-  // velocity); every other form reads the stored ones
+  // molecular weight, and the species enthalpies from T, above nine species
+  // (narrow stencil, correction velocity); every other form reads the
+  // stored ones
   const bool store_x = o->ns <= 9 || l.wide || l.ref_species >= 0;
   o->prims(l, U, P, F, react ? 2 : (ad ? 0 : 1), warm ? 1 : 0, store_x ? 1 : 0);
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
@@ -1704,7 +1705,7 @@ int rhs_vjp_g(sdc_context *c, Plan *p, const LaunchCtx &l, double *U, const doub
   double *P = W + L.P, *G = W + L.G;
   const FRef Uf{U, nullptr};
   o->ghost(l, Uf);
-  o->prims(l, Uf, P, FRef{nullptr, nullptr}, 0, 0, 1);   // the transposes read X
+  o->prims(l, Uf, P, FRef{nullptr, nullptr}, 0, 0, 1);   // the transposes read X and h
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
   adj_fill0(l, W + L.Pb, (long long)(L.Ub - L.Pb) + (long long)p->totS * nU);
   const AdjBufs ab{W + L.Ub, W + L.Pb, W + L.Gb};

@@ -189,8 +189,10 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       P[(L::PY + k) * nS + s] = Y[k];
-      if (store_x) P[(L::PX + k) * nS + s] = Y[k] * Wbar * m->invW[k];
-      P[(L::PH + k) * nS + s] = m->Rk[k] * T * h_RT(m, k, T, invT);
+      if (store_x) {
+        P[(L::PX + k) * nS + s] = Y[k] * Wbar * m->invW[k];
+        P[(L::PH + k) * nS + s] = m->Rk[k] * T * h_RT(m, k, T, invT);
+      }
     }
     if (out_mode == 0) continue;
     const int xi = x - NSDC_NG, yi = y - NSDC_NG, zi = z - NSDC_NG;
@@ -562,6 +564,24 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
         double rd[9], wp[9], u9[9], v[9], g[9], wb9[XLINE ? 9 : 1];
         line(P + L::PRD * nS, rd);
         if constexpr (XLINE) line(P + L::PWB * nS, wb9);
+        // h_k lines formed from the temperature line (h_k = R_k (T p_k(T) +
+        // a6_k), p_k the enthalpy polynomial) wherever the X_k lines are
+        constexpr bool HLINE = XLINE;
+        double T9[HLINE ? 9 : 1];
+        if constexpr (HLINE) line(P + L::PT * nS, T9);
+        auto hline = [&](int k, double *h) {
+          if constexpr (HLINE) {
+            const double *c = m->hc[k];
+            const double rk = m->Rk[k], a6 = m->h6[k];
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+              const double T = T9[o];
+              h[o] = rk * fma(T, c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * c[4]))), a6);
+            }
+          } else {
+            line(P + (L::PH + k) * nS, h);
+          }
+        };
         if constexpr (WIDE) {
           double w[17];
           line17(P + L::PP * nS, w);
@@ -654,7 +674,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
             } else if constexpr (XLINE) {
               // X_k = Y_k Wbar / W_k as the primitives kernel forms it
               line(P + (L::PY + k) * nS, y9);
-              line(P + (L::PH + k) * nS, g);
+              hline(k, g);
 #pragma unroll
               for (int o = 0; o < 9; ++o) u9[o] = y9[o] * wb9[o] * m->invW[k];
               BV(u9, v);
@@ -715,7 +735,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
             for (int o = 0; o < 9; ++o) u9[o] -= g[o];
             const double Lp = dot9(u9, wp);
             const double Lx = dot9(rd, v);
-            line(P + (L::PH + k) * nS, g);
+            hline(k, g);
             double LhX = 0.0, Lpe = 0.0;
 #pragma unroll
             for (int o = 0; o < 9; ++o) {
@@ -732,7 +752,7 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
 #pragma unroll 1
           for (int k = 0; k < NS; ++k) {
             line(P + (L::PY + k) * nS, u9);
-            line(P + (L::PH + k) * nS, g);
+            hline(k, g);
             const double DY = DD(u9);
             const double DhY = DDP(g, u9);
             spc(k) += u9[4] * divVc + Vc * DY;

@@ -51,8 +51,8 @@ struct Ops {
   void (*prim_to_cons)(const LaunchCtx &, const double *, const double *, const double *,
                        const double *, FRef);
   void (*ghost)(const LaunchCtx &, FRef);
-  // store_x = 0: leave the mole-fraction fields of P unwritten (no pass of
-  // the evaluation reads them)
+  // store_x = 0: leave the mole-fraction and species-enthalpy fields of P
+  // unwritten (no pass of the evaluation reads them)
   void (*prims)(const LaunchCtx &, FRef, double *, FRef, int out_mode, int warm, int store_x);
   void (*vgrad)(const LaunchCtx &, const double *, double *);
   void (*dir)(const LaunchCtx &, int, FRef, const double *, const double *, FRef, unsigned);
