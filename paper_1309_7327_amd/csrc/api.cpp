@@ -572,10 +572,10 @@ void eval_rhs_g(const Ops *o, const LaunchCtx &l, FRef U, double *P, double *G, 
   // into F (bit 8) and nothing clears it first
   const bool react = parts & RHS_REACT, ad = parts & RHS_AD;
   // the direction passes form the mole fractions from Y and the mean
-  // molecular weight, and the species enthalpies from T, above nine species
-  // (narrow stencil, correction velocity); every other form reads the
+  // molecular weight, and the species enthalpies from T (narrow stencil,
+  // correction velocity); the wide and reference-species forms read the
   // stored ones
-  const bool store_x = o->ns <= 9 || l.wide || l.ref_species >= 0;
+  const bool store_x = l.wide || l.ref_species >= 0;
   o->prims(l, U, P, F, react ? 2 : (ad ? 0 : 1), warm ? 1 : 0, store_x ? 1 : 0);
   if (parts & RHS_DIFF) o->vgrad(l, P, G);
   if (ad) {

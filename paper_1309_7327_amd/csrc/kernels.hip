@@ -264,8 +264,9 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
   }
 }
 
-// Occupancy: three workgroups per CU along x for up to 9 species (a small
-// spill), two otherwise (larger spills cost more than the extra waves gain).
+// Occupancy: two workgroups per CU (more spill, and the spills cost more than
+// the extra waves gain), three for the reference-species x pass of up to 9
+// species.
 // REF: the reference-species form of the species diffusion (its own
 // instance: the branch would otherwise raise the register use of both).
 // WIDE: the second-derivative pairs with the wide stencil D(a D u) of two
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
 // derivatives of the advective and of the diffusive terms, and the matrix K
 // of the second-derivative pairs in place of the face-difference matrix B.
 template <int NS, int D, bool FIXED, bool REF, bool WIDE, bool BND>
-__global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
+__global__ __launch_bounds__(256, D == 0 && NS <= 9 && REF && !WIDE && !BND ? 3 : 2) void k_dir(const BoxDev *__restrict__ boxes,
                                              const Item *__restrict__ items, int nitems,
                                              TileShape ts, FRef Uref,
                                              const double *__restrict__ Pbase,
@@ -557,10 +558,8 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
       // the energy pairs with h_k) and the correction velocity V_c,D, div V_c
       {
         // X_k lines formed from the Y_k lines and the mean molecular weight
-        // (the same bits as the stored X_k, one line fewer per species),
-        // except along x with up to nine species, where the extra live
-        // registers of the Wbar line spill
-        constexpr bool XLINE = !WIDE && !REF && (NS > 9 || D != 0);
+        // (the same bits as the stored X_k, one line fewer per species)
+        constexpr bool XLINE = !WIDE && !REF;
         double rd[9], wp[9], u9[9], v[9], g[9], wb9[XLINE ? 9 : 1];
         line(P + L::PRD * nS, rd);
         if constexpr (XLINE) line(P + L::PWB * nS, wb9);
@@ -671,18 +670,12 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && !WIDE && !BND ? 3 : 2) vo
               xpair(P + (L::PX + k) * nS, u9, v);
               line(P + (L::PY + k) * nS, y9);
               line(P + (L::PH + k) * nS, g);
-            } else if constexpr (XLINE) {
+            } else {
               // X_k = Y_k Wbar / W_k as the primitives kernel forms it
               line(P + (L::PY + k) * nS, y9);
               hline(k, g);
 #pragma unroll
               for (int o = 0; o < 9; ++o) u9[o] = y9[o] * wb9[o] * m->invW[k];
-              BV(u9, v);
-            } else {
-              // all three lines in flight before B X_k is formed
-              line(P + (L::PX + k) * nS, u9);
-              line(P + (L::PY + k) * nS, y9);
-              line(P + (L::PH + k) * nS, g);
               BV(u9, v);
             }
             const double DX = DD(u9);
