@@ -425,9 +425,12 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && REF && !WIDE && !BND ? 3 
 
     // with the diffusive terms on, the species convective terms of the y and
     // z passes join the species diffusion loop (more independent loads per
-    // iteration; along x the extra live registers spill)
-    constexpr bool HYP_IN_SPECIES = D != 0;
-    const bool hyp_species_apart = !HYP_IN_SPECIES || (parts & 2) == 0;
+    // iteration; along x the extra live registers spill); above nine species
+    // (correction velocity) they join the last species loop of every pass,
+    // as D_D(Y_k rho u_D) from the Y_k lines that loop loads anyway
+    constexpr bool CONV_IN_LAST = !SPEC_LDS && !REF;
+    constexpr bool HYP_IN_SPECIES = D != 0 && !CONV_IN_LAST;
+    const bool hyp_species_apart = CONV_IN_LAST ? (parts & 2) == 0 : (!HYP_IN_SPECIES || (parts & 2) == 0);
     if (parts & 1) {  // convective terms -D_D(F_D(U))
       double f[9];
 #pragma unroll
@@ -741,14 +744,24 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && REF && !WIDE && !BND ? 3 
             acc[4] += iLe * (LhX + Lpe) * idx2;
             Vc -= rd4 * iLe * (DX + dXY4 * Dpp);
           }
-          // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart with h_k Y_k
+          // Y_k (div V_c)_D + V_c,D D_D Y_k and the energy counterpart with
+          // h_k Y_k, and the convective terms with the momentum line along D
+          // (loaded again here: the barrier keeps the compiler from holding
+          // the convective part's copy live through the pass)
+          double m9[9];
+          if (parts & 1) {
+            asm volatile("" ::: "memory");
+            line(U + (1 + D) * nS, m9);
+          }
 #pragma unroll 1
           for (int k = 0; k < NS; ++k) {
             line(P + (L::PY + k) * nS, u9);
             hline(k, g);
             const double DY = DD(u9);
             const double DhY = DDP(g, u9);
-            spc(k) += u9[4] * divVc + Vc * DY;
+            double sk = u9[4] * divVc + Vc * DY;
+            if (parts & 1) sk -= DAP(u9, m9);
+            spc(k) += sk;
             acc[4] += g[4] * u9[4] * divVc + Vc * DhY;
           }
         }
