@@ -457,6 +457,14 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && REF && !WIDE && !BND ? 3 
     if (parts & 2) {  // diffusive terms
       const double bulk = m->bulk;
       const double lam2 = bulk - 2.0 / 3.0;
+      // X_k lines formed from the Y_k lines and the mean molecular weight
+      // (the same bits as the stored X_k, one line fewer per species), and
+      // h_k lines from the temperature line (h_k = R_k (T p_k(T) + a6_k), p_k
+      // the enthalpy polynomial); the temperature line, loaded once, also
+      // serves the heat conduction
+      constexpr bool XLINE = !WIDE && !REF;
+      constexpr bool HLINE = XLINE;
+      double T9[HLINE ? 9 : 1];
       if constexpr (WIDE) {
         // the same terms with the wide pairs
         double mu[9], ke[17], fe[9], w[17], v[9], g[9];
@@ -552,25 +560,22 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && REF && !WIDE && !BND ? 3 
         BV(ke, v);
         acc[4] += dot9(mu, v) * idx2 + DD(fe);
         // heat conduction L_D(lambda, T)
-        line(P + L::PT * nS, u9);
-        BV(u9, v);
+        if constexpr (HLINE) {
+          line(P + L::PT * nS, T9);
+          BV(T9, v);
+        } else {
+          line(P + L::PT * nS, u9);
+          BV(u9, v);
+        }
         line(P + L::PLAM * nS, g);
         acc[4] += dot9(g, v) * idx2;
       }
       // species diffusion (pairs (rho D_k, X_k), (rho D_k (X_k-Y_k)/p, p) and
       // the energy pairs with h_k) and the correction velocity V_c,D, div V_c
       {
-        // X_k lines formed from the Y_k lines and the mean molecular weight
-        // (the same bits as the stored X_k, one line fewer per species)
-        constexpr bool XLINE = !WIDE && !REF;
         double rd[9], wp[9], u9[9], v[9], g[9], wb9[XLINE ? 9 : 1];
         line(P + L::PRD * nS, rd);
         if constexpr (XLINE) line(P + L::PWB * nS, wb9);
-        // h_k lines formed from the temperature line (h_k = R_k (T p_k(T) +
-        // a6_k), p_k the enthalpy polynomial) wherever the X_k lines are
-        constexpr bool HLINE = XLINE;
-        double T9[HLINE ? 9 : 1];
-        if constexpr (HLINE) line(P + L::PT * nS, T9);
         auto hline = [&](int k, double *h) {
           if constexpr (HLINE) {
             const double *c = m->hc[k];
