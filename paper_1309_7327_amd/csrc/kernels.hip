@@ -1623,6 +1623,9 @@ template <int NS, int LANES = 1>
 __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<NS> &sl, const double *y,
                                    double rho, double T, double cv, double h, int sub = 0) {
   const double lnT = log(T), invT = 1.0 / T;
+  // keep the mechanism's coefficient loads here: hoisted out of the Newton
+  // iterations they outgrow the registers and are spilled and reloaded
+  asm volatile("" ::: "memory");
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     sl(sl.C + k) = y[k] * m->invW[k];
@@ -1681,7 +1684,9 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
   double dTdy[NS];
 #pragma unroll
   for (int c = 0; c < NS; ++c) dTdy[c] = -m->Rk[c] * T * (sl(sl.HR + c) - 1.0) * irc;
-#pragma unroll
+  // (rows as a loop above twelve species, as in mr2_solve)
+  constexpr int UROW = NS <= 12 ? NS : 1;
+#pragma unroll UROW
   for (int k = 0; k < NS; ++k) {
     const double hW = h * m->W[k], aT = sl(sl.AT + k);
 #pragma unroll
@@ -1693,7 +1698,11 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
 // A x = G in place (x in G) by Gaussian elimination with partial pivoting.
 template <int NS>
 __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
-#pragma unroll
+  // unrolled up to twelve species; beyond, the unrolled elimination's
+  // operands outgrow the registers (the 21-species kernel spilled 4.5 KB per
+  // lane), so the column loop runs as a loop
+  constexpr int UCOL = NS <= 12 ? NS : 1;
+#pragma unroll UCOL
   for (int col = 0; col < NS; ++col) {
     int piv = col;
     double best = fabs(sl.a(col, col));
@@ -1725,7 +1734,7 @@ __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
       sl(sl.G + r) -= f * sl(sl.G + col);
     }
   }
-#pragma unroll
+#pragma unroll UCOL
   for (int r = NS - 1; r >= 0; --r) {
     double x = sl(sl.G + r);
 #pragma unroll
