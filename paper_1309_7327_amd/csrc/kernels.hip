@@ -24,6 +24,8 @@
 //              a sum over D of Y_k (div V_c)_D + V_c,D D_D Y_k).
 #include <math.h>
 
+#include <type_traits>
+
 #include "nsdc_internal.h"
 
 #include "physics.h"
@@ -1605,22 +1607,66 @@ namespace nsdc {
 // (index NS of the last five is the dummy species of absent molecules); y
 // and b stay in registers.
 template <int NS>
-struct Mr2Slot {
-  double *p;
-  long long st;
+struct Mr2Layout {
   static constexpr int A = 0, G = NS * NS, C = G + NS, GR = C + NS + 1, HR = GR + NS + 1, AT = HR + NS + 1,
                        W = AT + NS + 1;
-  __device__ double &operator()(int i) const { return p[i * st]; }
-  __device__ double &a(int r, int c) const { return p[(r * NS + c) * st]; }
 };
-static_assert(Mr2Slot<21>::W + 22 == NSDC_MR2_SLOT(21), "mode-2 slot layout");
+static_assert(Mr2Layout<21>::W + 22 == NSDC_MR2_SLOT(21), "mode-2 slot layout");
+
+// A slot in LDS: entry i at p[i st].  LANES lanes share it (add: LDS atomics
+// for more than one).  ld/put take any index; ldv/putv are the same here.
+template <int NS, int LANES>
+struct Mr2SlotLds : Mr2Layout<NS> {
+  double *p;
+  int stride;
+  __device__ double ld(int i) const { return p[i * stride]; }
+  __device__ void put(int i, double v) const { p[i * stride] = v; }
+  __device__ double ldv(int i) const { return ld(i); }
+  __device__ void putv(int i, double v) const { put(i, v); }
+  __device__ void add(int i, double v) const {
+    if constexpr (LANES == 1)
+      p[i * stride] += v;
+    else
+      atomicAdd(p + i * stride, v);
+  }
+};
+
+// A lane's slot in a workspace region of NSDC_MR2_MAXWG * 256 lanes, entry i
+// of lane l at byte 8 (i NSDC_MR2_MAXWG 256 + l), through a buffer resource:
+// the lane's byte offset is its one vector offset and a wave-uniform index
+// times the fixed stride rides in the scalar offset (with the index in a
+// vector address every entry of an unrolled solve needed its own 64-bit
+// address, which the compiler hoisted and spilled).  ldv/putv take a
+// per-lane index (the pivot row) in the vector offset.
+template <int NS>
+struct Mr2SlotBuf : Mr2Layout<NS> {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  static constexpr int STRIDE = NSDC_MR2_MAXWG * 256 * 8;
+  __amdgpu_buffer_rsrc_t r;
+  int voff;
+  __device__ double ld(int i) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, i * STRIDE, 0));
+  }
+  __device__ void put(int i, double v) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, i * STRIDE, 0);
+  }
+  __device__ double ldv(int i) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff + i * STRIDE, 0, 0));
+  }
+  __device__ void putv(int i, double v) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff + i * STRIDE, 0, 0);
+  }
+  __device__ void add(int i, double v) const { put(i, ld(i) + v); }
+};
+static_assert((long long)NSDC_MR2_SLOT(NSDC_NSMAX) * NSDC_MR2_MAXWG * 256 * 8 < (1LL << 31),
+              "mode-2 workspace slots must stay within a buffer resource's signed offsets");
 
 // LANES = 2: the two lanes of a cell (32 apart in one wave) share its slot
 // in LDS; both write the same per-species values and form the same matrix
 // (identical writes), each takes every other reaction and adds its terms
 // with LDS atomics (a wave executes them in a fixed lane order).
-template <int NS, int LANES = 1>
-__device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<NS> &sl, const double *y,
+template <int NS, int LANES, class Slot>
+__device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Slot &sl, const double *y,
                                    double rho, double T, double cv, double h, int sub = 0) {
   const double lnT = log(T), invT = 1.0 / T;
   // keep the mechanism's coefficient loads here: hoisted out of the Newton
@@ -1628,40 +1674,36 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
   asm volatile("" ::: "memory");
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    sl(sl.C + k) = y[k] * m->invW[k];
-    sl(sl.GR + k) = g_RT(m, k, T, invT, lnT);
-    sl(sl.HR + k) = h_RT(m, k, T, invT);
-    sl(sl.AT + k) = 0.0;
-    sl(sl.W + k) = 0.0;
+    sl.put(sl.C + k, y[k] * m->invW[k]);
+    sl.put(sl.GR + k, g_RT(m, k, T, invT, lnT));
+    sl.put(sl.HR + k, h_RT(m, k, T, invT));
+    sl.put(sl.AT + k, 0.0);
+    sl.put(sl.W + k, 0.0);
 #pragma unroll
-    for (int c = 0; c < NS; ++c) sl.a(k, c) = 0.0;
+    for (int c = 0; c < NS; ++c) sl.put(sl.A + k * NS + c, 0.0);
   }
-  sl(sl.C + NS) = 1.0;
-  sl(sl.GR + NS) = 0.0;
-  sl(sl.HR + NS) = 0.0;
-  sl(sl.AT + NS) = 0.0;
-  sl(sl.W + NS) = 0.0;
+  sl.put(sl.C + NS, 1.0);
+  sl.put(sl.GR + NS, 0.0);
+  sl.put(sl.HR + NS, 0.0);
+  sl.put(sl.AT + NS, 0.0);
+  sl.put(sl.W + NS, 0.0);
   const double lnRTp = lnT + LN_RU_PREF;
   const int nr = m->nr;
-  auto add = [&](double &dst, double v) {
-    if constexpr (LANES == 1)
-      dst += v;
-    else
-      atomicAdd(&dst, v);
-  };
   if constexpr (LANES > 1) wave_sync();
   for (int j = sub; j < nr; j += LANES) {
     const int sp[4] = {m->rs[j][0], m->rs[j][1], m->ps[j][0], m->ps[j][1]};
     const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
-    const double dg = (sl(sl.GR + sp[2]) + sl(sl.GR + sp[3])) - (sl(sl.GR + sp[0]) + sl(sl.GR + sp[1]));
+    const double dg = (sl.ld(sl.GR + sp[2]) + sl.ld(sl.GR + sp[3])) - (sl.ld(sl.GR + sp[0]) + sl.ld(sl.GR + sp[1]));
     const double kf = exp(lnkf);
     const double kr = exp(lnkf + dg + m->dnu[j] * lnRTp);
-    const double c0 = sl(sl.C + sp[0]), c1 = sl(sl.C + sp[1]), c2 = sl(sl.C + sp[2]), c3 = sl(sl.C + sp[3]);
+    const double c0 = sl.ld(sl.C + sp[0]), c1 = sl.ld(sl.C + sp[1]), c2 = sl.ld(sl.C + sp[2]),
+                 c3 = sl.ld(sl.C + sp[3]);
     const double fwd = kf * c0 * c1, rev = kr * c2 * c3;
     const double q = fwd - rev;
     // d ln k_f / dT and d ln k_r / dT (d(g/RT)/dT = -(h/RT)/T)
     const double dlkf = (m->beta[j] + m->EaR[j] * invT) * invT;
-    const double ddg = -((sl(sl.HR + sp[2]) + sl(sl.HR + sp[3])) - (sl(sl.HR + sp[0]) + sl(sl.HR + sp[1]))) * invT;
+    const double ddg =
+        -((sl.ld(sl.HR + sp[2]) + sl.ld(sl.HR + sp[3])) - (sl.ld(sl.HR + sp[0]) + sl.ld(sl.HR + sp[1]))) * invT;
     const double dlkr = dlkf + ddg + m->dnu[j] * invT;
     const double dqdT = fwd * dlkf - rev * dlkr;
     // dq/dc of the four slots (a species twice gets both terms)
@@ -1670,12 +1712,12 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
     for (int i = 0; i < 4; ++i) {
       const double sgn = i < 2 ? -1.0 : 1.0;
       const int k = sp[i];
-      add(sl(sl.W + k), sgn * q);
-      add(sl(sl.AT + k), sgn * dqdT);
+      sl.add(sl.W + k, sgn * q);
+      sl.add(sl.AT + k, sgn * dqdT);
       if (k < NS)
 #pragma unroll
         for (int l = 0; l < 4; ++l)
-          if (sp[l] < NS) add(sl.a(k, sp[l]), sgn * dq[l] * m->invW[sp[l]]);
+          if (sp[l] < NS) sl.add(sl.A + k * NS + sp[l], sgn * dq[l] * m->invW[sp[l]]);
     }
   }
   if constexpr (LANES > 1) wave_sync();
@@ -1683,21 +1725,24 @@ __device__ void mr2_rates_jacobian(const DevMech *__restrict__ m, const Mr2Slot<
   const double irc = 1.0 / (rho * cv);
   double dTdy[NS];
 #pragma unroll
-  for (int c = 0; c < NS; ++c) dTdy[c] = -m->Rk[c] * T * (sl(sl.HR + c) - 1.0) * irc;
+  for (int c = 0; c < NS; ++c) dTdy[c] = -m->Rk[c] * T * (sl.ld(sl.HR + c) - 1.0) * irc;
   // (rows as a loop above twelve species, as in mr2_solve)
   constexpr int UROW = NS <= 12 ? NS : 1;
 #pragma unroll UROW
   for (int k = 0; k < NS; ++k) {
-    const double hW = h * m->W[k], aT = sl(sl.AT + k);
+    const double hW = h * m->W[k], aT = sl.ld(sl.AT + k);
 #pragma unroll
-    for (int c = 0; c < NS; ++c) sl.a(k, c) = (k == c ? 1.0 : 0.0) - hW * (sl.a(k, c) + aT * dTdy[c]);
-    sl(sl.W + k) *= m->W[k];
+    for (int c = 0; c < NS; ++c)
+      sl.put(sl.A + k * NS + c, (k == c ? 1.0 : 0.0) - hW * (sl.ld(sl.A + k * NS + c) + aT * dTdy[c]));
+    sl.put(sl.W + k, sl.ld(sl.W + k) * m->W[k]);
   }
 }
 
 // A x = G in place (x in G) by Gaussian elimination with partial pivoting.
-template <int NS>
-__device__ void mr2_solve(const Mr2Slot<NS> &sl) {
+template <int NS, class Slot>
+__device__ void mr2_solve(const Slot &sl) {
+  auto a = [&](int r, int c) { return sl.ld(sl.A + r * NS + c); };
+  auto seta = [&](int r, int c, double v) { sl.put(sl.A + r * NS + c, v); };
   // unrolled up to twelve species; beyond, the unrolled elimination's
   // operands outgrow the registers (the 21-species kernel spilled 4.5 KB per
   // lane), so the column loop runs as a loop
@@ -1705,41 +1750,42 @@ __device__ void mr2_solve(const Mr2Slot<NS> &sl) {
 #pragma unroll UCOL
   for (int col = 0; col < NS; ++col) {
     int piv = col;
-    double best = fabs(sl.a(col, col));
+    double best = fabs(a(col, col));
 #pragma unroll
     for (int r = col + 1; r < NS; ++r) {
-      const double v = fabs(sl.a(r, col));
+      const double v = fabs(a(r, col));
       if (v > best) {
         best = v;
         piv = r;
       }
     }
     if (piv != col) {
+      // (the pivot row differs between lanes: per-lane addressing)
 #pragma unroll
       for (int c = col; c < NS; ++c) {
-        const double t = sl.a(col, c);
-        sl.a(col, c) = sl.a(piv, c);
-        sl.a(piv, c) = t;
+        const double t = a(col, c);
+        seta(col, c, sl.ldv(sl.A + piv * NS + c));
+        sl.putv(sl.A + piv * NS + c, t);
       }
-      const double t = sl(sl.G + col);
-      sl(sl.G + col) = sl(sl.G + piv);
-      sl(sl.G + piv) = t;
+      const double t = sl.ld(sl.G + col);
+      sl.put(sl.G + col, sl.ldv(sl.G + piv));
+      sl.putv(sl.G + piv, t);
     }
-    const double inv = 1.0 / sl.a(col, col);
+    const double inv = 1.0 / a(col, col);
 #pragma unroll
     for (int r = col + 1; r < NS; ++r) {
-      const double f = sl.a(r, col) * inv;
+      const double f = a(r, col) * inv;
 #pragma unroll
-      for (int c = col + 1; c < NS; ++c) sl.a(r, c) -= f * sl.a(col, c);
-      sl(sl.G + r) -= f * sl(sl.G + col);
+      for (int c = col + 1; c < NS; ++c) seta(r, c, a(r, c) - f * a(col, c));
+      sl.put(sl.G + r, sl.ld(sl.G + r) - f * sl.ld(sl.G + col));
     }
   }
 #pragma unroll UCOL
   for (int r = NS - 1; r >= 0; --r) {
-    double x = sl(sl.G + r);
+    double x = sl.ld(sl.G + r);
 #pragma unroll
-    for (int c = r + 1; c < NS; ++c) x -= sl.a(r, c) * sl(sl.G + c);
-    sl(sl.G + r) = x / sl.a(r, r);
+    for (int c = r + 1; c < NS; ++c) x -= a(r, c) * sl.ld(sl.G + c);
+    sl.put(sl.G + r, x / a(r, r));
   }
 }
 
@@ -1763,8 +1809,19 @@ __global__ __launch_bounds__(LDS ? 64 : 256) void k_mr2_imp(const BoxDev *__rest
   static_assert(LANES == 1 || LDS, "lanes share a slot in LDS only");
   __shared__ double slot_sh[LDS ? NSDC_MR2_SLOT(NS) * CPP : 1];
   const int sub = LANES > 1 ? (int)threadIdx.x / CPP : 0, cslot = (int)threadIdx.x % CPP;
-  const Mr2Slot<NS> sl = LDS ? Mr2Slot<NS>{slot_sh + cslot, CPP}
-                             : Mr2Slot<NS>{a.J + (long long)blockIdx.x * blockDim.x + threadIdx.x, a.jstride};
+  // the slot: in LDS, or the lane's in the workspace region (at most
+  // NSDC_MR2_MAXWG workgroups of at most 256 lanes)
+  using Slot = std::conditional_t<LDS, Mr2SlotLds<NS, LANES>, Mr2SlotBuf<NS>>;
+  Slot sl;
+  if constexpr (LDS) {
+    sl.p = slot_sh + cslot;
+    sl.stride = CPP;
+  } else {
+    sl.r = __builtin_amdgcn_make_buffer_rsrc((void *)a.J, (short)0,
+                                             (int)((long long)NSDC_MR2_SLOT(NS) * Mr2SlotBuf<NS>::STRIDE),
+                                             0x00020000);
+    sl.voff = (int)(blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  }
   const int tcells = ts.tx * ts.ty * ts.tz;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
@@ -1814,12 +1871,12 @@ __global__ __launch_bounds__(LDS ? 64 : 256) void k_mr2_imp(const BoxDev *__rest
         for (int k = 0; k < NS; ++k) cv += Y[k] * m->Rk[k] * (cp_R(m, k, T) - 1.0);
         mr2_rates_jacobian<NS, LANES>(m, sl, yv, rho, T, cv, a.h, sub);
 #pragma unroll
-        for (int k = 0; k < NS; ++k) sl(sl.G + k) = yv[k] - a.h * sl(sl.W + k) - bv[k];
+        for (int k = 0; k < NS; ++k) sl.put(sl.G + k, yv[k] - a.h * sl.ld(sl.W + k) - bv[k]);
         mr2_solve<NS>(sl);
         double dmax = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-          const double d = sl(sl.G + k);
+          const double d = sl.ld(sl.G + k);
           yv[k] -= d;
           dmax = fmax(dmax, fabs(d));
         }
@@ -1836,7 +1893,7 @@ __global__ __launch_bounds__(LDS ? 64 : 256) void k_mr2_imp(const BoxDev *__rest
       mr2_rates_jacobian<NS, LANES>(m, sl, yv, rho, T, cv, a.h, sub);
 #pragma unroll
       for (int k = 0; k < NS; ++k)
-        if (LANES == 1 || k % LANES == sub) a.X[o1 + k * nI] = sl(sl.W + k);
+        if (LANES == 1 || k % LANES == sub) a.X[o1 + k * nI] = sl.ld(sl.W + k);
       if (errs) atomicOr(err, errs);
     }
   }
