@@ -266,8 +266,9 @@ struct sdc_context {
   bool fused_fine = true;               // one-kernel multirate fine sub-steps (4 coarse nodes, 4 sub-steps)
   double resid_ratio = 0.0;
   double *d_resid = nullptr;            // [NSDC_RESID_BLOCKS + 1][2 nU max] partial maxima, result
-  std::vector<double> resid_hist;       // residuals measured by the last sdc_step call
-  int last_sweeps = 0;                  // sweeps performed by the last sdc_step call
+  ResidCtl *d_rctl = nullptr;           // device state of the residual early exit
+  bool last_resid = false;              // the last sdc_step call decided its sweeps on the device
+  int last_sweeps = 0;                  // sweeps performed by the last sdc_step call (otherwise)
   std::map<std::string, hipGraphExec_t> graphs;
   // rhs_eval_static: this device's copy of the static scratch array, and a
   // pinned staging buffer (allocated here, at creation) through which the
@@ -522,6 +523,7 @@ int get_plan(sdc_context *c, int nbox, const box_desc *bx, double *const *U, Pla
 // d_boxes and d_items on the device.
 LaunchCtx make_lc_at(sdc_context *c, const Plan *p, BoxDev *d_boxes, Item *d_items, hipStream_t s) {
   LaunchCtx l;
+  l.skip = nullptr;
   l.stream = s;
   l.boxes = d_boxes;
   l.itemsI = d_items;
@@ -865,8 +867,15 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
     FRef Ub[2] = {FRef{W + L.Ub, nullptr}, FRef{W + L.Ub + fS, nullptr}};
     // residual early exit (eq. residual): q = last row of the integration
     // matrix, the sum of the node-to-node rows
+    // decided on the device: after each sweep but a step's last a kernel
+    // measures |R^k| and, once the sweeps stop approaching the collocation
+    // solution, sets a flag on which the stage kernels of the step's
+    // remaining sweeps return at once; no host synchronisation, so such
+    // steps can be captured in a graph too
     const bool resid = c->resid_ratio > 0.0;
     ResidArgs ra{};
+    LaunchCtx ls = l;
+    ResidCtl *ctl = c->d_rctl;
     if (resid) {
       for (int j = 0; j <= M; ++j)
         for (int m = 0; m < M; ++m) ra.q[j] += Sm[m][j];
@@ -874,21 +883,22 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
       ra.dt = dt;
       ra.partial = c->d_resid;
       ra.out = c->d_resid + (size_t)NSDC_RESID_BLOCKS * 2 * nU;
+      ls.skip = &ctl->stop;
+      launch_resid_ctl(st, ctl, 0, K);
     }
     eval_rhs_g(o, l, Uuser, P, G, FRef{F0, nullptr}, RHS_ALL);
     for (int step = 0; step < nsteps; ++step) {
       const double *Fold[8];
       for (int j = 0; j <= M; ++j) Fold[j] = F0;
       double *Fnew[8];
-      double rprev = -1.0;
-      int kdone = K;
+      if (resid && step > 0) launch_resid_ctl(st, ctl, 1, K);
       for (int k = 0; k < K; ++k) {
         const Range sweep_range("sweep");
         Fnew[0] = F0;
         for (int m = 1; m <= M; ++m) Fnew[m] = (k % 2 == 0) ? FA[m] : FB[m];
         FRef Ucur = Uuser;
         for (int m = 0; m < M; ++m) {
-          if (m > 0) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL, true);
+          if (m > 0) eval_rhs_g(o, ls, Ucur, P, G, FRef{Fnew[m], nullptr}, RHS_ALL, true);
           FRef Unext = (m == M - 1 && k == K - 1) ? Uuser : Ub[m % 2];
           NodeArgs a{};
           for (int j = 0; j <= M; ++j) {
@@ -900,34 +910,26 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
           a.Fold_m = Fold[m];
           a.dtau = dtau[m] * dt;
           a.dt = dt;
-          o->sdc_node(l, Ucur, Unext, a);
+          o->sdc_node(ls, Ucur, Unext, a);
           Ucur = Unext;
         }
         const bool last = step == nsteps - 1 && k == K - 1;
-        if (!last) eval_rhs_g(o, l, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL, true);
+        if (!last) eval_rhs_g(o, ls, Ucur, P, G, FRef{Fnew[M], nullptr}, RHS_ALL, true);
         for (int j = 0; j <= M; ++j) Fold[j] = Fnew[j];
         if (resid && k < K - 1) {
-          // |R^k| on the host (a synchronisation per sweep); stop the step's
-          // sweeps once it no longer shrinks by the ratio
           for (int j = 0; j <= M; ++j) ra.F[j] = Fnew[j];
-          o->sdc_resid(l, Uuser, Ucur, ra);
-          double h[2 * NSDC_NSMAX + 10];
-          HIPCHECK(c, hipMemcpyAsync(h, ra.out, sizeof(double) * 2 * nU, hipMemcpyDeviceToHost, st));
-          HIPCHECK(c, hipStreamSynchronize(st));
-          double r = 0.0;
-          for (int q = 0; q < nU; ++q)
-            if (h[nU + q] > 0.0) r = std::max(r, h[q] / h[nU + q]);
-          c->resid_hist.push_back(r);
-          if (r == 0.0 || (rprev >= 0.0 && rprev < c->resid_ratio * r)) {
-            // the step ends with this sweep's end state (in a sweep buffer)
-            HIPCHECK(c, hipMemcpyAsync(Uuser.base, Ucur.base, sizeof(double) * fS, hipMemcpyDeviceToDevice, st));
-            kdone = k + 1;
-            break;
-          }
-          rprev = r;
+          o->sdc_resid(ls, Uuser, Ucur, ra);
+          launch_resid_decide(st, ctl, ra.out, nU, c->resid_ratio, k);
+          // if this sweep ended the step, the step returns its end state (in
+          // a sweep buffer) and a next step recycles its f(U_M) from the
+          // array of the last sweep's, whose roles the host rotates below
+          double *Flast = ((K - 1) % 2 == 0) ? FA[M] : FB[M];
+          const bool recycle = step < nsteps - 1;
+          launch_resid_copy(st, ctl, k, Ucur.base, Uuser.base, fS, recycle ? Fnew[M] : nullptr,
+                            recycle ? Flast : nullptr, recycle ? fI : 0);
         }
       }
-      c->last_sweeps += kdone;
+      if (resid) launch_resid_ctl(st, ctl, 2, K);
       if (step < nsteps - 1) {
         // recycle f(U_M) as the next step's f(U_0): exchange array roles
         double *fin = Fnew[M];
@@ -1147,6 +1149,7 @@ int sdc_context_destroy(sdc_context *c) {
   c->fine_tabs.clear();
   c->d_fine = nullptr;
   if (c->d_resid) (void)hipFree(c->d_resid);
+  if (c->d_rctl) (void)hipFree(c->d_rctl);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   if (c->stage) (void)hipHostFree(c->stage);
   delete c;
@@ -1384,10 +1387,10 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
                int nsteps, const sdc_scheme *scheme, void *workspace, size_t ws_bytes,
                hipStream_t stream) {
   const Range range(nbox > 1 ? "sdc_step_batched" : "sdc_step");
-  c->resid_hist.clear();
-  c->last_sweeps = 0;
   if (c->resid_ratio > 0.0 && (nbox > 1 || scheme->n_fine != 0))
     return fail(c, SDC_EINVAL, "the residual early exit covers single-rate sdc_step only");
+  c->last_resid = c->resid_ratio > 0.0;
+  c->last_sweeps = scheme->sweeps * nsteps;
   Plan *pl;
   int rc = get_plan(c, nbox, boxes, nbox > 1 ? U : nullptr, &pl);
   if (rc) return rc;
@@ -1396,8 +1399,7 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
     rc = fine_tables(c, scheme);
     if (rc) return rc;
   }
-  // (the residual early exit reads residuals on the host: no graph)
-  if (!c->use_graph || !stream || c->prof || c->resid_ratio > 0.0) {
+  if (!c->use_graph || !stream || c->prof) {
     rc = run_sdc(c, pl, Uref, dt, nsteps, scheme, workspace, ws_bytes, stream);
     if (rc) return rc;
     HIPCHECK(c, hipGetLastError());
@@ -1409,11 +1411,11 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
   // fine-sweep form)
   char buf[320];
   const bool tables = scheme->n_fine != 0 && scheme->mode != 2;
-  snprintf(buf, sizeof buf, "|%p|%.17g|%d|%d,%d,%d,%d,m%d|%p|%zu|%p|ns%d|w%d|ref%d|ff%d|smc%d|%p", (void *)pl,
+  snprintf(buf, sizeof buf, "|%p|%.17g|%d|%d,%d,%d,%d,m%d|%p|%zu|%p|ns%d|w%d|ref%d|ff%d|smc%d|%p|rr%.17g", (void *)pl,
            dt, nsteps, scheme->n_coarse, scheme->sweeps, scheme->n_fine, scheme->fine_repeat,
            scheme->mode == 2 ? 2 : 1, workspace, ws_bytes, nbox > 1 ? nullptr : (void *)U[0], c->ops->ns,
            (int)c->wide, c->h_mech.ref, (int)c->fused_fine, (int)c->smc_stencil,
-           tables ? (void *)c->d_fine : nullptr);
+           tables ? (void *)c->d_fine : nullptr, c->resid_ratio);
   const std::string key = buf;
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
@@ -1493,6 +1495,8 @@ int sdc_set_residual_exit(sdc_context *c, double ratio) {
   if (ratio > 0.0 && !c->d_resid) {
     HIPCHECK(c, hipSetDevice(c->device));
     HIPCHECK(c, hipMalloc(&c->d_resid, sizeof(double) * (NSDC_RESID_BLOCKS + 1) * 2 * (5 + NSDC_NSMAX)));
+    HIPCHECK(c, hipMalloc(&c->d_rctl, sizeof(ResidCtl)));
+    HIPCHECK(c, hipMemset(c->d_rctl, 0, sizeof(ResidCtl)));
   }
   c->resid_ratio = ratio;
   return SDC_OK;
@@ -1500,10 +1504,19 @@ int sdc_set_residual_exit(sdc_context *c, double ratio) {
 
 int sdc_residual_history(const sdc_context *c, int max, double *norms, int *count, int *sweeps) {
   if (!c || max < 0 || (max > 0 && !norms)) return SDC_EINVAL;
-  const int n = (int)c->resid_hist.size();
-  for (int i = 0; i < n && i < max; ++i) norms[i] = c->resid_hist[i];
+  if (!c->last_resid) {
+    if (count) *count = 0;
+    if (sweeps) *sweeps = c->last_sweeps;
+    return SDC_OK;
+  }
+  // the decisions live on the device: wait for the call, then read them
+  if (hipSetDevice(c->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return SDC_EHIP;
+  ResidCtl h;
+  if (hipMemcpy(&h, c->d_rctl, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) return SDC_EHIP;
+  const int n = std::min(h.count, NSDC_RESID_HIST);
+  for (int i = 0; i < n && i < max; ++i) norms[i] = h.hist[i];
   if (count) *count = n;
-  if (sweeps) *sweeps = c->last_sweeps;
+  if (sweeps) *sweeps = h.sweeps;
   return SDC_OK;
 }
 

@@ -84,7 +84,8 @@ __global__ __launch_bounds__(256) void k_prim_to_cons(const BoxDev *__restrict__
 template <int NCOMP>
 __global__ __launch_bounds__(256) void k_ghost(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
-                                               FRef Uref) {
+                                               FRef Uref, const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a residual early exit ended the step's sweeps
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -141,7 +142,9 @@ __global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
                                                TileShape ts, FRef Uref, double *__restrict__ Pbase,
                                                FRef Fout, int out_mode, int warm, int store_x,
-                                               const DevMech *__restrict__ m, int *err) {
+                                               const DevMech *__restrict__ m, int *err,
+                                               const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a residual early exit ended the step's sweeps
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
   constexpr int LIM = CHEM ? 65536 : 0;
@@ -222,7 +225,9 @@ template <int NS>
 __global__ __launch_bounds__(256) void k_vgrad(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
                                                TileShape ts, const double *__restrict__ Pbase,
-                                               double *__restrict__ Gbase, const DevMech *__restrict__ m) {
+                                               double *__restrict__ Gbase, const DevMech *__restrict__ m,
+                                               const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a residual early exit ended the step's sweeps
   using L = Layout<NS>;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
@@ -288,7 +293,9 @@ __global__ __launch_bounds__(256, D == 0 && NS <= 9 && REF && !WIDE && !BND ? 3 
                                              TileShape ts, FRef Uref,
                                              const double *__restrict__ Pbase,
                                              const double *__restrict__ Gbase, FRef Fout,
-                                             unsigned parts, const DevMech *__restrict__ m) {
+                                             unsigned parts, const DevMech *__restrict__ m,
+                                             const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a residual early exit ended the step's sweeps
   using L = Layout<NS>;
   constexpr int NU = L::NU, NP = L::NP;
   constexpr int J1 = D == 0 ? 1 : 0, J2 = D == 2 ? 1 : 2;   // the two other directions
@@ -841,7 +848,8 @@ template <int NS>
 __global__ __launch_bounds__(256) void k_sdc_node(const BoxDev *__restrict__ boxes,
                                                   const Item *__restrict__ items, int nitems,
                                                   TileShape ts, FRef Ucur, FRef Unext,
-                                                  NodeArgs a) {
+                                                  NodeArgs a, const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a residual early exit ended the step's sweeps
   constexpr int NU = 5 + NS;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
@@ -872,7 +880,8 @@ __global__ __launch_bounds__(256) void k_sdc_node(const BoxDev *__restrict__ box
 template <int NS>
 __global__ __launch_bounds__(256) void k_sdc_resid(const BoxDev *__restrict__ boxes,
                                                    const Item *__restrict__ items, int nitems,
-                                                   TileShape ts, FRef U0ref, FRef UMref, ResidArgs a) {
+                                                   TileShape ts, FRef U0ref, FRef UMref, ResidArgs a, const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a residual early exit ended the step's sweeps
   constexpr int NU = 5 + NS;
   __shared__ double red[256];
   double rmax[NU], umax[NU];
@@ -917,7 +926,9 @@ __global__ __launch_bounds__(256) void k_sdc_resid(const BoxDev *__restrict__ bo
 // out[v] = max over the nblocks rows of partial[.][v]: workgroup v of ncol,
 // 256 threads striding over the rows, then a tree in LDS.
 __global__ __launch_bounds__(256) void k_rows_max(const double *__restrict__ partial, int nblocks, int ncol,
-                                                  double *__restrict__ out) {
+                                                  double *__restrict__ out,
+                                                  const int *__restrict__ skip) {
+  if (skip && *skip) return;   // a residual early exit ended the step's sweeps
   __shared__ double red[256];
   const int v = blockIdx.x, t = threadIdx.x;
   double m = 0.0;
@@ -1932,6 +1943,69 @@ __global__ __launch_bounds__(256) void k_mr2_node(const BoxDev *__restrict__ box
   }
 }
 
+// ------------------------------------------------ residual early exit
+// Bookkeeping of the device-side decision (one thread): op 0 at the start of
+// an sdc_step call (no residuals, no sweeps yet) and of its first step, op 1
+// at the start of every later step, op 2 at the end of each step (the sweeps
+// it took: those up to the one that ended it, else all K).
+__global__ void k_resid_ctl(ResidCtl *ctl, int op, int K) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (op == 0) {
+    ctl->count = 0;
+    ctl->sweeps = 0;
+  }
+  if (op <= 1) {
+    ctl->stop = 0;
+    ctl->rprev = -1.0;
+  }
+  if (op == 2) ctl->sweeps += ctl->stop ? ctl->stop : K;
+}
+
+// After sweep k (from 0) of a step: |R^k| = max_c max|R_c| / max|U_0,c| from
+// the reduced maxima out[0..2 nU) (components with a zero denominator left
+// out), recorded; the step's sweeps end once it no longer shrinks by the
+// ratio (or is exactly zero).
+__global__ void k_resid_decide(ResidCtl *ctl, const double *__restrict__ out, int nU, double ratio, int k) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || ctl->stop) return;
+  double r = 0.0;
+  for (int q = 0; q < nU; ++q)
+    if (out[nU + q] > 0.0) r = fmax(r, out[q] / out[nU + q]);
+  if (ctl->count < NSDC_RESID_HIST) ctl->hist[ctl->count] = r;
+  ctl->count += 1;
+  if (r == 0.0 || (ctl->rprev >= 0.0 && ctl->rprev < ratio * r))
+    ctl->stop = k + 1;
+  else
+    ctl->rprev = r;
+}
+
+// If sweep k ended the step: its end state into the state the step returns
+// (n1 doubles) and, when a next step recycles it, its f(U_M) into the array
+// the last sweep's would occupy (n2 doubles; nothing when the two coincide).
+__global__ __launch_bounds__(256) void k_resid_copy(const ResidCtl *__restrict__ ctl, int k,
+                                                    const double *__restrict__ Us, double *__restrict__ Ud,
+                                                    long long n1, const double *Fs, double *Fd, long long n2) {
+  if (ctl->stop != k + 1) return;
+  if (Fs == Fd) n2 = 0;
+  const long long n = n1 + n2, step = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    if (i < n1)
+      Ud[i] = Us[i];
+    else
+      Fd[i - n1] = Fs[i - n1];
+  }
+}
+
+void launch_resid_ctl(hipStream_t s, ResidCtl *ctl, int op, int K) {
+  hipLaunchKernelGGL(k_resid_ctl, dim3(1), dim3(64), 0, s, ctl, op, K);
+}
+void launch_resid_decide(hipStream_t s, ResidCtl *ctl, const double *out, int nU, double ratio, int k) {
+  hipLaunchKernelGGL(k_resid_decide, dim3(1), dim3(64), 0, s, ctl, out, nU, ratio, k);
+}
+void launch_resid_copy(hipStream_t s, const ResidCtl *ctl, int k, const double *Us, double *Ud, long long n1,
+                       const double *Fs, double *Fd, long long n2) {
+  hipLaunchKernelGGL(k_resid_copy, dim3(1024), dim3(256), 0, s, ctl, k, Us, Ud, n1, Fs, Fd, n2);
+}
+
 static inline int grid_for(int nitems, int cap) { return nitems < cap ? (nitems > 0 ? nitems : 1) : cap; }
 
 template <int NS>
@@ -1946,7 +2020,7 @@ struct Launch {
   static void ghost(const LaunchCtx &c, FRef U) {
     prof_begin(c.prof, K_GHOST, c.stream);
     hipLaunchKernelGGL(k_ghost<5 + NS>, dim3(grid_for(c.nG, c.cap)), dim3(256), 0, c.stream, c.boxes,
-                       c.itemsG, c.nG, U);
+                       c.itemsG, c.nG, U, c.skip);
     prof_end(c.prof, K_GHOST, c.stream);
   }
   static void prims(const LaunchCtx &c, FRef U, double *P, FRef F, int out_mode, int warm, int store_x) {
@@ -1954,16 +2028,16 @@ struct Launch {
     const dim3 grid(grid_for(c.nS, c.cap)), block(c.tsS.tx * c.tsS.ty * c.tsS.tz);
     if (out_mode == 2)
       hipLaunchKernelGGL((k_prims<NS, true>), grid, block, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F,
-                         out_mode, warm, store_x, c.mech, c.err);
+                         out_mode, warm, store_x, c.mech, c.err, c.skip);
     else
       hipLaunchKernelGGL((k_prims<NS, false>), grid, block, 0, c.stream, c.boxes, c.itemsS, c.nS, c.tsS, U, P, F,
-                         out_mode, warm, store_x, c.mech, c.err);
+                         out_mode, warm, store_x, c.mech, c.err, c.skip);
     prof_end(c.prof, K_PRIMS, c.stream);
   }
   static void vgrad(const LaunchCtx &c, const double *P, double *G) {
     prof_begin(c.prof, K_VGRAD, c.stream);
     hipLaunchKernelGGL(k_vgrad<NS>, dim3(grid_for(c.nS, c.cap)), dim3(c.tsS.tx * c.tsS.ty * c.tsS.tz), 0,
-                       c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, G, c.mech);
+                       c.stream, c.boxes, c.itemsS, c.nS, c.tsS, P, G, c.mech, c.skip);
     prof_end(c.prof, K_VGRAD, c.stream);
   }
   template <int D, bool FIXED, bool REF, bool WIDE>
@@ -1971,7 +2045,7 @@ struct Launch {
     const TileShape ts = c.tsD[D];
     const dim3 grid(grid_for(c.nD[D], c.cap)), block(ts.tx * ts.ty * ts.tz);
     hipLaunchKernelGGL((k_dir<NS, D, FIXED, REF, WIDE, false>), grid, block, 0, c.stream, c.boxes, c.itemsD[D],
-                       c.nD[D], ts, U, P, G, F, parts, c.mech);
+                       c.nD[D], ts, U, P, G, F, parts, c.mech, c.skip);
     // the boundary layers of boxes with physical boundaries along D (the
     // wide stencil is rejected with them)
     if constexpr (!WIDE) {
@@ -1979,7 +2053,7 @@ struct Launch {
         const TileShape tb = c.tsB[D];
         hipLaunchKernelGGL((k_dir<NS, D, FIXED, REF, false, true>), dim3(grid_for(c.nB[D], c.cap)),
                            dim3(tb.tx * tb.ty * tb.tz), 0, c.stream, c.boxes, c.itemsB[D], c.nB[D], tb, U, P, G, F,
-                           parts, c.mech);
+                           parts, c.mech, c.skip);
       }
     }
   }
@@ -2023,15 +2097,16 @@ struct Launch {
   static void sdc_node(const LaunchCtx &c, FRef Ucur, FRef Unext, const NodeArgs &a) {
     prof_begin(c.prof, K_SDC_NODE, c.stream);
     hipLaunchKernelGGL(k_sdc_node<NS>, dim3(grid_for(c.nI, c.cap)), dim3(c.tsI.tx * c.tsI.ty * c.tsI.tz), 0,
-                       c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Ucur, Unext, a);
+                       c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Ucur, Unext, a, c.skip);
     prof_end(c.prof, K_SDC_NODE, c.stream);
   }
   static void sdc_resid(const LaunchCtx &c, FRef U0, FRef UM, const ResidArgs &a) {
     const int nb = grid_for(c.nI, NSDC_RESID_BLOCKS);
     prof_begin(c.prof, K_SDC_RESID, c.stream);
     hipLaunchKernelGGL(k_sdc_resid<NS>, dim3(nb), dim3(c.tsI.tx * c.tsI.ty * c.tsI.tz), 0, c.stream, c.boxes,
-                       c.itemsI, c.nI, c.tsI, U0, UM, a);
-    hipLaunchKernelGGL(k_rows_max, dim3(2 * (5 + NS)), dim3(256), 0, c.stream, a.partial, nb, 2 * (5 + NS), a.out);
+                       c.itemsI, c.nI, c.tsI, U0, UM, a, c.skip);
+    hipLaunchKernelGGL(k_rows_max, dim3(2 * (5 + NS)), dim3(256), 0, c.stream, a.partial, nb, 2 * (5 + NS), a.out,
+                       c.skip);
     prof_end(c.prof, K_SDC_RESID, c.stream);
   }
   static void mr2_imp(const LaunchCtx &c, FRef Ucur, const Mr2Imp &a) {

@@ -44,6 +44,10 @@ struct LaunchCtx {
   int ref_species;    // species diffusion: -1 correction velocity, else the reference species
   bool wide;          // second-derivative pairs with the wide stencil D(a D u)
   bool fused_fine;    // multirate fine sub-steps in one kernel where it applies
+  // device flag of the residual early exit (null: none): non-zero once a
+  // step's sweeps have ended, the stage kernels of the rest of the step
+  // return at once
+  const int *skip;
 };
 
 struct Ops {
@@ -63,6 +67,12 @@ struct Ops {
   void (*mr2_imp)(const LaunchCtx &, FRef, const Mr2Imp &);
   void (*mr2_node)(const LaunchCtx &, FRef, FRef, const Mr2Node &);
 };
+
+// residual early exit decided on the device (kernels.hip)
+void launch_resid_ctl(hipStream_t s, ResidCtl *ctl, int op, int K);
+void launch_resid_decide(hipStream_t s, ResidCtl *ctl, const double *out, int nU, double ratio, int k);
+void launch_resid_copy(hipStream_t s, const ResidCtl *ctl, int k, const double *Us, double *Ud, long long n1,
+                       const double *Fs, double *Fd, long long n2);
 
 // nullptr for an unsupported species count
 const Ops *ops_for(int ns);

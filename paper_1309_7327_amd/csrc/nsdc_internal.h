@@ -108,6 +108,18 @@ struct ResidArgs {
   double *partial, *out;
 };
 
+// Device state of the residual early exit over one sdc_step call: stop is
+// 0 while the current step sweeps, else the number of sweeps it took (the
+// stage kernels of its remaining sweeps return at once); rprev the step's
+// previous residual; count the residuals measured in the call (the first
+// NSDC_RESID_HIST of them in hist); sweeps the sweeps the call performed.
+#define NSDC_RESID_HIST 4096
+struct ResidCtl {
+  int stop, count, sweeps, pad;
+  double rprev;
+  double hist[NSDC_RESID_HIST];
+};
+
 // Coefficients of one coarse interval of the multirate sweep, in units of
 // the step: rows of S_{2,1} and S_{2,2} restricted to the interval's fine
 // nodes, and the fine sub-step lengths (device memory, one per interval).

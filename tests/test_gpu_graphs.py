@@ -1,6 +1,7 @@
 """Captured step graphs follow every change of what they depend on: the
 stencil variant, the species-diffusion form, the fine-sweep form, the
-mechanism and the multirate scheme.  Each graph replay is compared bit for
+mechanism and the multirate scheme, and steps with the residual early exit.
+Each graph replay is compared bit for
 bit with an eager (uncaptured) run of the same configuration, with eager
 work and synchronisations between the replays."""
 import numpy as np
@@ -85,6 +86,43 @@ def test_graphs_follow_setters_and_schemes():
                 got = G.host(G.interior(U))
                 assert np.array_equal(got, ref[ci, si]), (cfgs[ci], si, rep)
                 torch.cuda.synchronize()
+    finally:
+        ctx.set_graph(False)
+        ctx.close()
+
+
+def test_residual_exit_steps_replay_from_graphs():
+    """The residual early exit decides on the device, so its steps are
+    captured too: replays of a two-step call give the eager call's state,
+    residuals and sweep count bit for bit, with eager work between them,
+    and the exit really skipped sweeps."""
+    mech = mechanism.load("mech9")
+    ctx = N.Context(0)
+    ctx.set_mechanism(mech)
+    ctx.set_residual_exit(30.0)
+    prim = fields.sines((8, 8, 8), DX, 9, 13)
+    bx, U0 = G.device_state(ctx, prim, DX)
+    dt = time_step("box16_sdc")
+    stream = torch.cuda.Stream()
+    sch = N.scheme(4, 14, 0, 1)
+    ctx.set_graph(False)
+    ref = _run(ctx, bx, U0, sch, dt, 2, stream)
+    ref_norms, ref_sweeps = ctx.residual_history()
+    assert 0 < ref_sweeps < 2 * 14 and len(ref_norms) > 0
+    ctx.set_graph(True)
+    try:
+        U = U0.clone()
+        ws, nb = N.workspace(ctx, [bx], sch)
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                U.copy_(U0)
+            stream.synchronize()
+            ctx.sdc_step(bx, U, dt, 2, sch, ws, nb, stream=stream.cuda_stream)
+            ctx.check_status(stream.cuda_stream)
+            assert np.array_equal(G.host(G.interior(U)), ref), rep
+            norms, sweeps = ctx.residual_history()
+            assert sweeps == ref_sweeps and np.array_equal(norms, ref_norms), rep
+            torch.cuda.synchronize()
     finally:
         ctx.set_graph(False)
         ctx.close()
