@@ -217,17 +217,17 @@ int sdc_set_fused_fine(sdc_context *ctx, int enable);
  * sweep but a step's last and skips the step's remaining sweeps once
  * |R^{k-1}| / |R^k| < ratio (the sweeps no longer approach the collocation
  * solution).  |R| is the largest over state components of max|R_c| /
- * max|U_0,c| over the interior.  The decision is taken on the device (the
- * stage kernels of a step's skipped sweeps are launched and return at once),
- * so the call does not synchronise the stream and may be captured in a
- * graph like any other.  Covers single-rate sdc_step on one box:
- * sdc_step_batched and
- * multirate schemes return SDC_EINVAL while it is on, and so do rhs_vjp and
- * sdc_step_vjp.  Enabling it allocates a small device buffer (kept until the
+ * max|U_0,c| over the interior; for sdc_step_batched both maxima run over
+ * every box of the batch, whose boxes share the decision.  The decision is
+ * taken on the device (the stage kernels of a step's skipped sweeps are
+ * launched and return at once), so the call does not synchronise the stream
+ * and may be captured in a graph like any other.  Covers single-rate
+ * schemes: multirate schemes return SDC_EINVAL while it is on, and so do
+ * rhs_vjp and sdc_step_vjp.  Enabling it allocates a small device buffer (kept until the
  * context is destroyed).  Errors: SDC_EINVAL for 0 < ratio <= 1 or ratio < 0. */
 int sdc_set_residual_exit(sdc_context *ctx, double ratio);
 
-/* The residuals |R^k| measured by the last sdc_step call, in order (the
+/* The residuals |R^k| measured by the last sdc_step or sdc_step_batched call, in order (the
  * first max of them into norms, host memory), how many there were
  * (count, at most 4096 are kept) and the sweeps the call performed over all
  * its steps (sweeps); count and sweeps may be null.  After a call with the

@@ -925,7 +925,7 @@ int run_sdc(sdc_context *c, Plan *p, FRef Uuser, double dt, int nsteps, const sd
           // array of the last sweep's, whose roles the host rotates below
           double *Flast = ((K - 1) % 2 == 0) ? FA[M] : FB[M];
           const bool recycle = step < nsteps - 1;
-          launch_resid_copy(st, ctl, k, Ucur.base, Uuser.base, fS, recycle ? Fnew[M] : nullptr,
+          launch_resid_copy(st, ctl, k, l.boxes, p->nbox, nU, Ucur.base, Uuser, recycle ? Fnew[M] : nullptr,
                             recycle ? Flast : nullptr, recycle ? fI : 0);
         }
       }
@@ -1387,8 +1387,8 @@ int step_entry(sdc_context *c, int nbox, const box_desc *boxes, double *const *U
                int nsteps, const sdc_scheme *scheme, void *workspace, size_t ws_bytes,
                hipStream_t stream) {
   const Range range(nbox > 1 ? "sdc_step_batched" : "sdc_step");
-  if (c->resid_ratio > 0.0 && (nbox > 1 || scheme->n_fine != 0))
-    return fail(c, SDC_EINVAL, "the residual early exit covers single-rate sdc_step only");
+  if (c->resid_ratio > 0.0 && scheme->n_fine != 0)
+    return fail(c, SDC_EINVAL, "the residual early exit covers single-rate schemes only");
   c->last_resid = c->resid_ratio > 0.0;
   c->last_sweeps = scheme->sweeps * nsteps;
   Plan *pl;

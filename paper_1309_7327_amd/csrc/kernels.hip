@@ -1978,21 +1978,25 @@ __global__ void k_resid_decide(ResidCtl *ctl, const double *__restrict__ out, in
     ctl->rprev = r;
 }
 
-// If sweep k ended the step: its end state into the state the step returns
-// (n1 doubles) and, when a next step recycles it, its f(U_M) into the array
+// If sweep k ended the step: its end state (the sweep buffer Us, every box's
+// nU stored fields at the box's offset) into the states the step returns
+// (Ud, per box) and, when a next step recycles it, its f(U_M) into the array
 // the last sweep's would occupy (n2 doubles; nothing when the two coincide).
 __global__ __launch_bounds__(256) void k_resid_copy(const ResidCtl *__restrict__ ctl, int k,
-                                                    const double *__restrict__ Us, double *__restrict__ Ud,
-                                                    long long n1, const double *Fs, double *Fd, long long n2) {
+                                                    const BoxDev *__restrict__ boxes, int nbox, int nU,
+                                                    const double *__restrict__ Us, FRef Ud, const double *Fs,
+                                                    double *Fd, long long n2) {
   if (ctl->stop != k + 1) return;
-  if (Fs == Fd) n2 = 0;
-  const long long n = n1 + n2, step = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
-    if (i < n1)
-      Ud[i] = Us[i];
-    else
-      Fd[i - n1] = Fs[i - n1];
+  const long long step = (long long)gridDim.x * blockDim.x, t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int bx = 0; bx < nbox; ++bx) {
+    const BoxDev b = boxes[bx];
+    const long long off = b.offS * nU, n = (long long)b.sx * b.sy * b.sz * nU;
+    const double *src = Us + off;
+    double *dst = Ud.get(bx, off);
+    for (long long i = t0; i < n; i += step) dst[i] = src[i];
   }
+  if (Fs != Fd)
+    for (long long i = t0; i < n2; i += step) Fd[i] = Fs[i];
 }
 
 void launch_resid_ctl(hipStream_t s, ResidCtl *ctl, int op, int K) {
@@ -2001,9 +2005,9 @@ void launch_resid_ctl(hipStream_t s, ResidCtl *ctl, int op, int K) {
 void launch_resid_decide(hipStream_t s, ResidCtl *ctl, const double *out, int nU, double ratio, int k) {
   hipLaunchKernelGGL(k_resid_decide, dim3(1), dim3(64), 0, s, ctl, out, nU, ratio, k);
 }
-void launch_resid_copy(hipStream_t s, const ResidCtl *ctl, int k, const double *Us, double *Ud, long long n1,
-                       const double *Fs, double *Fd, long long n2) {
-  hipLaunchKernelGGL(k_resid_copy, dim3(1024), dim3(256), 0, s, ctl, k, Us, Ud, n1, Fs, Fd, n2);
+void launch_resid_copy(hipStream_t s, const ResidCtl *ctl, int k, const BoxDev *boxes, int nbox, int nU,
+                       const double *Us, FRef Ud, const double *Fs, double *Fd, long long n2) {
+  hipLaunchKernelGGL(k_resid_copy, dim3(1024), dim3(256), 0, s, ctl, k, boxes, nbox, nU, Us, Ud, Fs, Fd, n2);
 }
 
 static inline int grid_for(int nitems, int cap) { return nitems < cap ? (nitems > 0 ? nitems : 1) : cap; }

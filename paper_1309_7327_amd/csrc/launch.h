@@ -71,8 +71,8 @@ struct Ops {
 // residual early exit decided on the device (kernels.hip)
 void launch_resid_ctl(hipStream_t s, ResidCtl *ctl, int op, int K);
 void launch_resid_decide(hipStream_t s, ResidCtl *ctl, const double *out, int nU, double ratio, int k);
-void launch_resid_copy(hipStream_t s, const ResidCtl *ctl, int k, const double *Us, double *Ud, long long n1,
-                       const double *Fs, double *Fd, long long n2);
+void launch_resid_copy(hipStream_t s, const ResidCtl *ctl, int k, const BoxDev *boxes, int nbox, int nU,
+                       const double *Us, FRef Ud, const double *Fs, double *Fd, long long n2);
 
 // nullptr for an unsupported species count
 const Ops *ops_for(int ns);

@@ -78,6 +78,81 @@ def test_residual_exit_parity(kind, shape, K, ratio, nsteps):
     ctx.close()
 
 
+def _flat_sdc(om, U0s, dx, dt, K, nsteps, ratio, hist=None):
+    """The oracle's step of several boxes advanced together: their interiors
+    side by side along one cell axis, the right-hand side evaluated box by
+    box, so the residual (and the exit decision) is the batch's.  Returns
+    step(V, perturb) on the joined state and the split back into boxes."""
+    nc = U0s[0].shape[0]
+    sizes = [u[0].size for u in U0s]
+
+    def split(V):
+        out, o = [], 0
+        for u, n in zip(U0s, sizes):
+            out.append(V[:, o:o + n].reshape(u.shape))
+            o += n
+        return out
+
+    def f(V, t):
+        return np.concatenate([oracle.rhs(om, p, dx).reshape(nc, -1) for p in split(V)], axis=1)
+
+    def step(V, pt):
+        return osdc.sdc_run(f, V, 0.0, dt, osdc.gauss_lobatto(4), K, nsteps, pt, residual_ratio=ratio,
+                            history=hist if pt is None else None)
+
+    return step, split, np.concatenate([u.reshape(nc, -1) for u in U0s], axis=1)
+
+
+def test_residual_exit_batched_parity():
+    """Boxes advanced by one sdc_step_batched call share the exit decision:
+    |R| is taken over all their interiors (the largest over components of
+    max|R_c| / max|U_0,c|, both maxima over the batch).  Against the oracle
+    run on the boxes joined along one cell axis."""
+    m, om, ctx = _ctx("mech9")
+    ratio, K, nsteps = 30.0, 14, 2
+    ctx.set_residual_exit(ratio)
+    dt = time_step("box16_sdc")
+    boxes, Us, U0s = [], [], []
+    for shape, seed in (((8, 8, 8), 13), ((6, 5, 7), 21)):
+        bx, U, U0 = G.oracle_state(om, fields.sines(shape, 1e-4, m["ns"], seed), 1e-4)
+        boxes.append(bx)
+        Us.append(U)
+        U0s.append(U0)
+    s = N.scheme(4, K, 0, 1)
+    ws, nb = N.workspace(ctx, boxes, s)
+    ctx.sdc_step_batched(boxes, Us, dt, nsteps, s, ws, nb)
+    ctx.check_status()
+    norms, sweeps = ctx.residual_history()
+    hist = []
+    step, split, V0 = _flat_sdc(om, U0s, 1e-4, dt, K, nsteps, ratio, hist)
+    Vend, floor, dfloor = G.ulp_floor_step(step, V0)
+    ref = split(Vend)
+    rs = np.array([h[2] for h in hist if h[0] != "sweeps"])
+    osw = [h[1] for h in hist if h[0] == "sweeps"]
+    print("sweeps", sweeps, osw, "residuals", norms, rs)
+    # decisions far from the threshold (ratios 110 and 6.8, then 60 and 13)
+    prev = None
+    for h in hist:
+        if h[0] == "sweeps":
+            prev = None
+            continue
+        assert h[2] > 1e-10
+        if prev is not None:
+            assert abs(np.log(prev / h[2]) - np.log(ratio)) > np.log(1.05), (prev, h[2])
+        prev = h[2]
+    assert sweeps == sum(osw) < nsteps * K
+    assert len(norms) == len(rs)
+    np.testing.assert_allclose(norms, rs, rtol=1e-6, atol=1e-14)
+    for U, r, U0 in zip(Us, ref, U0s):
+        Ug = G.interior(G.host(U))
+        ok, rep = G.compare(Ug, r, floor)
+        okd, repd = G.compare(Ug - U0, r - U0, dfloor, state=r)
+        print("U ", G.fmt(rep))
+        print("dU", G.fmt(repd))
+        assert ok and okd, G.fmt(repd)
+    ctx.close()
+
+
 def test_residual_exit_off_is_the_fixed_sweep_step_and_errors():
     m, om, ctx = _ctx("mech9")
     shape = (8, 9, 10)
