@@ -1101,16 +1101,61 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The chemistry source of one cell on a lane pair: lanes sub = 0 and 1 share
+// the cell's LDS column sh, with b_k, G_k and the production w_k at offsets
+// 0, A and 2 A and slot k at k CS (the rate form of production()).  Each lane
+// sets up every other slot (slot 2 n + sub, the dummy slot NS included, so
+// the pair forms each exponential b_k once), then takes every other reaction
+// (coefficients from the workgroup's LDS copies rsp, rco) and adds its rate of
+// progress into w with LDS atomics.  On return w holds the cell's
+// sum_j nu_kj q_j.
+template <int NS, int CS>
+__device__ __forceinline__ void pair_rates(const DevMech *__restrict__ m, double rho, double T, const double *Y,
+                                           double *sh, int sub, const int (*rsp)[4], const double (*rco)[4],
+                                           const double *tab, int nr) {
+  constexpr int A = (NS + 1) * CS;
+  const double lnT = log(T), invT = 1.0 / T, lnRTp = lnT + LN_RU_PREF;
+  double *shs = sh + sub * CS;
+  wave_sync();   // the previous readers of this column are done
+#pragma unroll
+  for (int n = 0; n < (NS + 2) / 2; ++n) {
+    const int k0 = 2 * n, k1 = 2 * n + 1;
+    const int i0 = k0 < NS ? k0 : NS - 1, i1 = k1 < NS ? k1 : NS - 1;
+    const double g0 = k0 < NS ? g_RT(m, i0, T, invT, lnT) : -lnRTp;
+    const double c0 = k0 < NS ? rho * Y[i0] * m->invW[i0] : 1.0;
+    const double g1 = k1 < NS ? g_RT(m, i1, T, invT, lnT) : -lnRTp;
+    const double c1 = k1 < NS ? rho * Y[i1] * m->invW[i1] : 1.0;
+    if (k1 <= NS || sub == 0) {
+      const double g = sub ? g1 : g0, c = sub ? c1 : c0;
+      shs[A + k0 * CS] = g;
+      shs[k0 * CS] = c * exp_tab(g, tab);
+      shs[2 * A + k0 * CS] = 0.0;
+    }
+  }
+  wave_sync();
+#pragma unroll 4
+  for (int j = sub; j < nr; j += 2) {
+    const int r0 = rsp[j][0], r1 = rsp[j][1], p0 = rsp[j][2], p1 = rsp[j][3];
+    const double lnkf = rco[j][0] + rco[j][1] * lnT - rco[j][2] * invT;
+    const double kf = exp_tab(lnkf - (sh[A + r0] + sh[A + r1]), tab);
+    const double q = kf * (sh[r0] * sh[r1] - sh[p0] * sh[p1]);
+    atomicAdd(sh + 2 * A + r0, -q);
+    atomicAdd(sh + 2 * A + r1, -q);
+    atomicAdd(sh + 2 * A + p0, q);
+    atomicAdd(sh + 2 * A + p1, q);
+  }
+  wave_sync();
+}
+
 // k_mr_step with two lanes per cell, for more than nine species.  A cell's
-// chemistry arrays (concentrations, Gibbs energies, production: 3 (Ns+1)
-// doubles, 528 bytes at 21 species) in LDS allowed one wave per SIMD with a
-// lane per cell; two lanes sharing a cell's column halve the LDS per lane, so
-// two waves per SIMD fit.  Both lanes of a pair run the cell's state update,
-// Newton solve and species setup (redundantly, same values), then each takes
-// every other reaction (its coefficients from an LDS copy of the mechanism's
-// reaction table, the lanes now being on different reactions) and adds its
-// rates into the shared production array with LDS atomics; each lane writes
-// half of the outputs.  A workgroup's lanes (whole waves, at most 256) cover
+// chemistry arrays (b_k, Gibbs energies, production: 3 (Ns+1) doubles, 528
+// bytes at 21 species) in LDS allowed one wave per SIMD with a lane per cell;
+// two lanes sharing a cell's column halve the LDS per lane, so two waves per
+// SIMD fit.  Both lanes of a pair run the cell's state update and Newton
+// solve (redundantly, same values), then split the species setup and the
+// reactions between them (pair_rates: the reaction coefficients from an LDS
+// copy of the mechanism's reaction table, the lanes being on different
+// reactions); each lane writes half of the outputs.  A workgroup's lanes (whole waves, at most 256) cover
 // the cells of a work item in two passes of half as many.
 template <int NS>
 __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ boxes,
@@ -1123,7 +1168,7 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
   __shared__ double col[3 * A];
   __shared__ double tab[64];
   __shared__ int rsp[NSDC_NRMAX][4];       // reactant and product slots, times CS
-  __shared__ double rco[NSDC_NRMAX][4];    // ln A, beta, Ea/R, sum of nu
+  __shared__ double rco[NSDC_NRMAX][4];    // ln A, beta, Ea/R (the fourth entry pads)
   const int nr = m->nr;
   for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = m->e2tab[j];
   for (int j = threadIdx.x; j < nr; j += blockDim.x) {
@@ -1134,7 +1179,6 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
     rco[j][0] = m->lnA[j];
     rco[j][1] = m->beta[j];
     rco[j][2] = m->EaR[j];
-    rco[j][3] = (double)m->dnu[j];
   }
   __syncthreads();
   // lane l of wave v: cell slot 32 v + (l mod 32), reaction parity l / 32 (the
@@ -1145,33 +1189,7 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
   double *sh = col + slot;
   // the chemistry source of one cell, rates split between the two lanes
   auto production_pair = [&](double rho, double T, const double *Y, double *wdot) {
-    const double lnT = log(T), invT = 1.0 / T;
-    wave_sync();   // the previous sub-step's reads of this column are done
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      sh[k * CS] = rho * Y[k] * m->invW[k];
-      sh[A + k * CS] = g_RT(m, k, T, invT, lnT);
-      sh[2 * A + k * CS] = 0.0;
-    }
-    sh[NS * CS] = 1.0;
-    sh[A + NS * CS] = 0.0;
-    sh[2 * A + NS * CS] = 0.0;
-    wave_sync();
-    const double lnRTp = lnT + LN_RU_PREF;
-#pragma unroll 4
-    for (int j = sub; j < nr; j += 2) {
-      const int r0 = rsp[j][0], r1 = rsp[j][1], p0 = rsp[j][2], p1 = rsp[j][3];
-      const double lnkf = rco[j][0] + rco[j][1] * lnT - rco[j][2] * invT;
-      const double dg = (sh[A + p0] + sh[A + p1]) - (sh[A + r0] + sh[A + r1]);
-      const double kf = exp_tab(lnkf, tab);
-      const double kr = exp_tab(lnkf + dg + rco[j][3] * lnRTp, tab);
-      const double q = kf * sh[r0] * sh[r1] - kr * sh[p0] * sh[p1];
-      atomicAdd(sh + 2 * A + r0, -q);
-      atomicAdd(sh + 2 * A + r1, -q);
-      atomicAdd(sh + 2 * A + p0, q);
-      atomicAdd(sh + 2 * A + p1, q);
-    }
-    wave_sync();
+    pair_rates<NS, CS>(m, rho, T, Y, sh, sub, rsp, rco, tab, nr);
 #pragma unroll
     for (int k = 0; k < NS; ++k) wdot[k] = sh[2 * A + k * CS] * m->W[k];
   };
@@ -1262,40 +1280,13 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
     rco[j][0] = m->lnA[j];
     rco[j][1] = m->beta[j];
     rco[j][2] = m->EaR[j];
-    rco[j][3] = (double)m->dnu[j];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, slot = (threadIdx.x >> 6) * 32 + (lane & 31), sub = lane >> 5;
   double *sh = col + slot;
   // as in k_mr_pair
   auto production_pair = [&](double rho, double T, const double *Y, double *wdot) {
-    const double lnT = log(T), invT = 1.0 / T;
-    wave_sync();
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      sh[k * CS] = rho * Y[k] * m->invW[k];
-      sh[A + k * CS] = g_RT(m, k, T, invT, lnT);
-      sh[2 * A + k * CS] = 0.0;
-    }
-    sh[NS * CS] = 1.0;
-    sh[A + NS * CS] = 0.0;
-    sh[2 * A + NS * CS] = 0.0;
-    wave_sync();
-    const double lnRTp = lnT + LN_RU_PREF;
-#pragma unroll 4
-    for (int j = sub; j < nr; j += 2) {
-      const int r0 = rsp[j][0], r1 = rsp[j][1], p0 = rsp[j][2], p1 = rsp[j][3];
-      const double lnkf = rco[j][0] + rco[j][1] * lnT - rco[j][2] * invT;
-      const double dg = (sh[A + p0] + sh[A + p1]) - (sh[A + r0] + sh[A + r1]);
-      const double kf = exp_tab(lnkf, tab);
-      const double kr = exp_tab(lnkf + dg + rco[j][3] * lnRTp, tab);
-      const double q = kf * sh[r0] * sh[r1] - kr * sh[p0] * sh[p1];
-      atomicAdd(sh + 2 * A + r0, -q);
-      atomicAdd(sh + 2 * A + r1, -q);
-      atomicAdd(sh + 2 * A + p0, q);
-      atomicAdd(sh + 2 * A + p1, q);
-    }
-    wave_sync();
+    pair_rates<NS, CS>(m, rho, T, Y, sh, sub, rsp, rco, tab, nr);
     // this lane's species only
 #pragma unroll
     for (int n = 0; n < NK; ++n) {

@@ -116,32 +116,36 @@ __device__ int temperature(const DevMech *__restrict__ m, const double *Y, doubl
 // reverse rate from the equilibrium constant of the Gibbs energies):
 //   k_r = k_f exp(sum nu g/RT) (R T / p_ref)^{sum nu}.
 // Every reaction has two reactant and two product slots; an absent molecule
-// points at slot NS, a dummy species with concentration 1 and g = 0, so the
-// loop body has no branches.
+// points at slot NS, a dummy species.  The rate of progress is formed with
+// one exponential per reaction: with G_k = g_k/RT, b_k = c_k exp(G_k) and the
+// dummy slot's G = -ln(R T / p_ref), c = 1 (so that sum nu = the number of
+// absent reactant molecules minus absent product molecules is carried by
+// the slots),
+//   q = k_f c_r0 c_r1 - k_r c_p0 c_p1 = exp(ln k_f - G_r0 - G_r1) (b_r0 b_r1 - b_p0 b_p1),
+// which costs NS + 1 exponentials per cell for the b_k instead of one more
+// per reaction.  The loop body has no branches.
 template <int NS>
 __device__ void production(const DevMech *__restrict__ m, double rho, double T, const double *Y,
                            double *wdot) {
-  double c[NS + 1], g[NS + 1], w[NS + 1];
+  double b[NS + 1], g[NS + 1], w[NS + 1];
   const double lnT = log(T), invT = 1.0 / T;
+  const double lnRTp = lnT + LN_RU_PREF;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    c[k] = rho * Y[k] * m->invW[k];
     g[k] = g_RT(m, k, T, invT, lnT);
+    b[k] = rho * Y[k] * m->invW[k] * exp(g[k]);
     w[k] = 0.0;
   }
-  c[NS] = 1.0;
-  g[NS] = 0.0;
+  g[NS] = -lnRTp;
+  b[NS] = exp(-lnRTp);
   w[NS] = 0.0;
-  const double lnRTp = lnT + LN_RU_PREF;
   const int nr = m->nr;
 #pragma unroll 2
   for (int j = 0; j < nr; ++j) {
     const int r0 = m->rs[j][0], r1 = m->rs[j][1], p0 = m->ps[j][0], p1 = m->ps[j][1];
     const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
-    const double dg = (g[p0] + g[p1]) - (g[r0] + g[r1]);
-    const double kf = exp(lnkf);
-    const double kr = exp(lnkf + dg + m->dnu[j] * lnRTp);
-    const double q = kf * c[r0] * c[r1] - kr * c[p0] * c[p1];
+    const double kf = exp(lnkf - (g[r0] + g[r1]));
+    const double q = kf * (b[r0] * b[r1] - b[p0] * b[p1]);
     w[r0] -= q;
     w[r1] -= q;
     w[p0] += q;
@@ -151,7 +155,7 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
   for (int k = 0; k < NS; ++k) wdot[k] = w[k] * m->W[k];
 }
 
-// The same source with the per-cell arrays c, g and w in this thread's LDS
+// The same source with the per-cell arrays b, g and w in this thread's LDS
 // column: entry k of array a at sh[(a (NS+1) + k) 256] (consecutive threads
 // own consecutive doubles).  A species index then costs one address add
 // shared by the three arrays, instead of indexed register moves.  The
@@ -167,26 +171,25 @@ __device__ void production_sh(const DevMech *__restrict__ m, double rho, double 
                               double *wdot, double *sh, const double *tab) {
   constexpr int S = 256, A = (NS + 1) * S;
   const double lnT = log(T), invT = 1.0 / T;
+  const double lnRTp = lnT + LN_RU_PREF;
   asm volatile("" ::: "memory");
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    sh[k * S] = rho * Y[k] * m->invW[k];
-    sh[A + k * S] = g_RT(m, k, T, invT, lnT);
+    const double g = g_RT(m, k, T, invT, lnT);
+    sh[A + k * S] = g;
+    sh[k * S] = rho * Y[k] * m->invW[k] * exp_tab(g, tab);
     sh[2 * A + k * S] = 0.0;
   }
-  sh[NS * S] = 1.0;
-  sh[A + NS * S] = 0.0;
+  sh[A + NS * S] = -lnRTp;
+  sh[NS * S] = exp_tab(-lnRTp, tab);
   sh[2 * A + NS * S] = 0.0;
-  const double lnRTp = lnT + LN_RU_PREF;
   const int nr = m->nr;
 #pragma unroll 4
   for (int j = 0; j < nr; ++j) {
     const int r0 = m->rs[j][0] * S, r1 = m->rs[j][1] * S, p0 = m->ps[j][0] * S, p1 = m->ps[j][1] * S;
     const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
-    const double dg = (sh[A + p0] + sh[A + p1]) - (sh[A + r0] + sh[A + r1]);
-    const double kf = exp_tab(lnkf, tab);
-    const double kr = exp_tab(lnkf + dg + m->dnu[j] * lnRTp, tab);
-    const double q = kf * sh[r0] * sh[r1] - kr * sh[p0] * sh[p1];
+    const double kf = exp_tab(lnkf - (sh[A + r0] + sh[A + r1]), tab);
+    const double q = kf * (sh[r0] * sh[r1] - sh[p0] * sh[p1]);
     atomicAdd(sh + 2 * A + r0, -q);
     atomicAdd(sh + 2 * A + r1, -q);
     atomicAdd(sh + 2 * A + p0, q);
