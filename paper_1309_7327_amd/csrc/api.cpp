@@ -33,8 +33,6 @@ using namespace nsdc;
 
 namespace {
 
-constexpr double RU = 8.31446261815324;
-
 // ------------------------------------------------------------- quadrature
 // Legendre polynomial P_n and its derivative at x (three-term recurrence).
 void legendre(int n, long double x, long double &p, long double &dp) {
@@ -1229,6 +1227,24 @@ int set_mechanism(sdc_context *c, const mechanism_desc *m) {
     for (int i = nr_; i < 2; ++i) d.rs[j][i] = m->ns;
     for (int i = np_; i < 2; ++i) d.ps[j][i] = m->ns;
     d.dnu[j] = dnu;
+    // the reactants' Gibbs energies folded into the forward rate's exponent
+    double *x = d.xc[j];
+    x[0] = d.lnA[j];
+    x[1] = d.beta[j];
+    x[2] = -d.EaR[j];
+    x[3] = x[4] = x[5] = x[6] = x[7] = 0.0;
+    for (int i = 0; i < 2; ++i) {
+      const int k = d.rs[j][i];
+      if (k == m->ns) {   // the dummy slot: G = -ln T - ln(R_u / p_ref)
+        x[0] += LN_RU_PREF;
+        x[1] += 1.0;
+        continue;
+      }
+      x[0] -= d.gc[k][0];
+      x[1] += d.cp[k][0];
+      x[2] -= d.h6[k];
+      for (int p = 1; p < 5; ++p) x[2 + p] -= d.gc[k][p];
+    }
   }
   // eighth-order narrow-stencil matrix M(m47, m48), Section 2.2: rows 1..4
   // as printed, rows 5..8 the negated reversals of rows 4..1.

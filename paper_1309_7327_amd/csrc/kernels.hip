@@ -1101,62 +1101,103 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The chemistry source of one cell on a lane pair: lanes sub = 0 and 1 share
-// the cell's LDS column sh, with b_k, G_k and the production w_k at offsets
-// 0, A and 2 A and slot k at k CS (the rate form of production()).  Each lane
-// sets up every other slot (slot 2 n + sub, the dummy slot NS included, so
-// the pair forms each exponential b_k once), then takes every other reaction
-// (coefficients from the workgroup's LDS copies rsp, rco) and adds its rate of
-// progress into w with LDS atomics.  On return w holds the cell's
-// sum_j nu_kj q_j.
+// Lane pairs for more than nine species: a cell's chemistry arrays in LDS
+// (b_k and two production arrays: 3 (Ns+1) doubles, 528 bytes at 21 species)
+// would allow one wave per SIMD with a lane per cell; two lanes sharing a
+// cell's column halve the LDS per lane, so two waves per SIMD fit.  The two
+// lanes of a cell are lane l of waves 2v and 2v + 1 of a 256-thread
+// workgroup (cell slot 64 v + l): the lane's half, sub = the wave's parity, is
+// uniform over a wave, so the species and reactions a lane takes are the
+// same for its whole wave and their coefficients come from scalar loads of
+// the mechanism.  Each lane sums its reactions' contributions into its own
+// production array, in reaction order, and the two arrays are added in a
+// fixed order, so the result does not depend on how the two waves
+// interleave.  The pair's exchanges through LDS synchronise the workgroup,
+// so every thread runs every pass of the cell loop (lanes without a cell
+// compute on the tile's first cell and store nothing).
+struct PairLane {
+  int sub, slot;
+  __device__ PairLane() {
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    sub = wv & 1;
+    slot = (wv >> 1) * 64 + (int)(threadIdx.x & 63);
+  }
+};
+
+// Lane SUB's reactions j = SUB, SUB + 2, ...: their rates of progress
+// (production()'s form) added into its production array (offset (1 + SUB) A
+// of the column; b_k at offset 0).
+template <int NS, int CS, int SUB>
+__device__ __forceinline__ void pair_loop(const DevMech *__restrict__ m, double T, double invT, double lnT,
+                                          double *sh, const double *tab) {
+  constexpr int A = (NS + 1) * CS, WO = (1 + SUB) * A;
+  const int nr = m->nr;
+#pragma unroll 4
+  for (int j = SUB; j < nr; j += 2) {
+    const int r0 = m->rs[j][0] * CS, r1 = m->rs[j][1] * CS, p0 = m->ps[j][0] * CS, p1 = m->ps[j][1] * CS;
+    const double q = exp_tab(rate_exponent(m, j, T, invT, lnT), tab) * (sh[r0] * sh[r1] - sh[p0] * sh[p1]);
+    atomicAdd(sh + WO + r0, -q);
+    atomicAdd(sh + WO + r1, -q);
+    atomicAdd(sh + WO + p0, q);
+    atomicAdd(sh + WO + p1, q);
+  }
+}
+
+// The chemistry source of one cell on a lane pair: the pair's LDS column sh
+// holds b_k and the lanes' production arrays at offsets 0, A and 2 A, slot k
+// at k CS.  Lane sub sets up the slots k = sub, sub + 2, ... (the dummy slot
+// NS included, so the pair forms each exponential b_k once), clears its
+// production array and takes its reactions.  Every thread of the workgroup
+// calls it; on return the cell's production of slot k is
+// sh[A + k CS] + sh[2 A + k CS].
 template <int NS, int CS>
 __device__ __forceinline__ void pair_rates(const DevMech *__restrict__ m, double rho, double T, const double *Y,
-                                           double *sh, int sub, const int (*rsp)[4], const double (*rco)[4],
-                                           const double *tab, int nr) {
+                                           double *sh, int sub, const double *tab) {
   constexpr int A = (NS + 1) * CS;
   const double lnT = log(T), invT = 1.0 / T, lnRTp = lnT + LN_RU_PREF;
-  double *shs = sh + sub * CS;
-  wave_sync();   // the previous readers of this column are done
+  __syncthreads();   // the previous readers of the columns are done
 #pragma unroll
   for (int n = 0; n < (NS + 2) / 2; ++n) {
     const int k0 = 2 * n, k1 = 2 * n + 1;
-    const int i0 = k0 < NS ? k0 : NS - 1, i1 = k1 < NS ? k1 : NS - 1;
-    const double g0 = k0 < NS ? g_RT(m, i0, T, invT, lnT) : -lnRTp;
-    const double c0 = k0 < NS ? rho * Y[i0] * m->invW[i0] : 1.0;
-    const double g1 = k1 < NS ? g_RT(m, i1, T, invT, lnT) : -lnRTp;
-    const double c1 = k1 < NS ? rho * Y[i1] * m->invW[i1] : 1.0;
     if (k1 <= NS || sub == 0) {
-      const double g = sub ? g1 : g0, c = sub ? c1 : c0;
-      shs[A + k0 * CS] = g;
-      shs[k0 * CS] = c * exp_tab(g, tab);
-      shs[2 * A + k0 * CS] = 0.0;
+      const int k = k0 + sub;
+      const double y = sub ? Y[k1 < NS ? k1 : NS - 1] : Y[k0 < NS ? k0 : NS - 1];
+      sh[k * CS] = k < NS ? rho * y * m->invW[k] * exp_tab(g_RT(m, k, T, invT, lnT), tab) : exp_tab(-lnRTp, tab);
     }
   }
-  wave_sync();
-#pragma unroll 4
-  for (int j = sub; j < nr; j += 2) {
-    const int r0 = rsp[j][0], r1 = rsp[j][1], p0 = rsp[j][2], p1 = rsp[j][3];
-    const double lnkf = rco[j][0] + rco[j][1] * lnT - rco[j][2] * invT;
-    const double kf = exp_tab(lnkf - (sh[A + r0] + sh[A + r1]), tab);
-    const double q = kf * (sh[r0] * sh[r1] - sh[p0] * sh[p1]);
-    atomicAdd(sh + 2 * A + r0, -q);
-    atomicAdd(sh + 2 * A + r1, -q);
-    atomicAdd(sh + 2 * A + p0, q);
-    atomicAdd(sh + 2 * A + p1, q);
-  }
-  wave_sync();
+  double *wo = sh + (1 + sub) * A;
+#pragma unroll
+  for (int k = 0; k <= NS; ++k) wo[k * CS] = 0.0;
+  __syncthreads();
+  if (sub == 0)
+    pair_loop<NS, CS, 0>(m, T, invT, lnT, sh, tab);
+  else
+    pair_loop<NS, CS, 1>(m, T, invT, lnT, sh, tab);
+  __syncthreads();
 }
 
-// k_mr_step with two lanes per cell, for more than nine species.  A cell's
-// chemistry arrays (b_k, Gibbs energies, production: 3 (Ns+1) doubles, 528
-// bytes at 21 species) in LDS allowed one wave per SIMD with a lane per cell;
-// two lanes sharing a cell's column halve the LDS per lane, so two waves per
-// SIMD fit.  Both lanes of a pair run the cell's state update and Newton
-// solve (redundantly, same values), then split the species setup and the
-// reactions between them (pair_rates: the reaction coefficients from an LDS
-// copy of the mechanism's reaction table, the lanes being on different
-// reactions); each lane writes half of the outputs.  A workgroup's lanes (whole waves, at most 256) cover
-// the cells of a work item in two passes of half as many.
+// The cell of pass h (a multiple of 128) of a work item for pair slot `slot`:
+// false (and the tile's first cell, which every work item has) when the slot
+// has no cell in this pass.
+__device__ __forceinline__ bool pair_cell(const Item &w, const BoxDev &b, const TileShape &ts, int h, int slot,
+                                          unsigned &s, unsigned &i) {
+  const int cell = h + slot;
+  int x = w.x0 + cell % ts.tx, y = w.y0 + (cell / ts.tx) % ts.ty, z = w.z0 + cell / (ts.tx * ts.ty);
+  const bool valid = cell < ts.tx * ts.ty * ts.tz && x < b.nx && y < b.ny && z < b.nz;
+  if (!valid) {
+    x = w.x0;
+    y = w.y0;
+    z = w.z0;
+  }
+  s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
+  i = ((unsigned)z * b.ny + y) * b.nx + x;
+  return valid;
+}
+
+// k_mr_step on lane pairs (above): both lanes of a pair run the cell's state
+// update and Newton solve (redundantly, same values) and split the species
+// setup and the reactions (pair_rates); each lane writes half of the outputs.
+// Launched with 256 threads whatever the tile: 128 cells per pass.
 template <int NS>
 __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ boxes,
                                                     const Item *__restrict__ items, int nitems,
@@ -1167,32 +1208,17 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
   constexpr int NU = 5 + NS, CS = 128, A = (NS + 1) * CS;
   __shared__ double col[3 * A];
   __shared__ double tab[64];
-  __shared__ int rsp[NSDC_NRMAX][4];       // reactant and product slots, times CS
-  __shared__ double rco[NSDC_NRMAX][4];    // ln A, beta, Ea/R (the fourth entry pads)
-  const int nr = m->nr;
   for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = m->e2tab[j];
-  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
-    rsp[j][0] = m->rs[j][0] * CS;
-    rsp[j][1] = m->rs[j][1] * CS;
-    rsp[j][2] = m->ps[j][0] * CS;
-    rsp[j][3] = m->ps[j][1] * CS;
-    rco[j][0] = m->lnA[j];
-    rco[j][1] = m->beta[j];
-    rco[j][2] = m->EaR[j];
-  }
-  __syncthreads();
-  // lane l of wave v: cell slot 32 v + (l mod 32), reaction parity l / 32 (the
-  // two lanes of a cell 32 apart in one wave, so each group of sixteen lanes
-  // that the LDS serves together works on one species of sixteen neighbouring
-  // cells: consecutive doubles, no bank conflicts)
-  const int lane = threadIdx.x & 63, slot = (threadIdx.x >> 6) * 32 + (lane & 31), sub = lane >> 5;
-  double *sh = col + slot;
+  const PairLane pl;
+  const int sub = pl.sub;
+  double *sh = col + pl.slot;
   // the chemistry source of one cell, rates split between the two lanes
   auto production_pair = [&](double rho, double T, const double *Y, double *wdot) {
-    pair_rates<NS, CS>(m, rho, T, Y, sh, sub, rsp, rco, tab, nr);
+    pair_rates<NS, CS>(m, rho, T, Y, sh, sub, tab);
 #pragma unroll
-    for (int k = 0; k < NS; ++k) wdot[k] = sh[2 * A + k * CS] * m->W[k];
+    for (int k = 0; k < NS; ++k) wdot[k] = (sh[A + k * CS] + sh[2 * A + k * CS]) * m->W[k];
   };
+  const int tcells = ts.tx * ts.ty * ts.tz;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -1202,12 +1228,9 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
     double *Uo = Uout.get(w.box, b.offS * NU);
     auto F2 = [&](int slot, int k) { return fp.F2base + (slot * fp.f2slot + o2 + k * nI); };
     auto Af = [&](int r, int q) { return Abase + (r * aslot + o1 + q * nI); };
-    for (int h = 0; h < 2; ++h) {
-      const int cell = h * (int)(blockDim.x >> 1) + slot;
-      const int x = w.x0 + cell % ts.tx, y = w.y0 + (cell / ts.tx) % ts.ty, z = w.z0 + cell / (ts.tx * ts.ty);
-      if (cell >= ts.tx * ts.ty * ts.tz || x >= b.nx || y >= b.ny || z >= b.nz) continue;
-      const unsigned s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
-      const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
+    for (int h = 0; h < tcells; h += CS) {
+      unsigned s, i;
+      const bool valid = pair_cell(w, b, ts, h, pl.slot, s, i);
       double Uc[NU];
 #pragma unroll
       for (int q = 0; q < NU; ++q) Uc[q] = (Ui + q * nS)[s];
@@ -1224,9 +1247,10 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
           errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
           Tprev = T;
           production_pair(rho, T, Y, f2);
+          if (valid)
 #pragma unroll
-          for (int k = 0; k < NS; ++k)
-            if ((k & 1) == sub) F2(fp.F2new[qq], k)[i] = f2[k];
+            for (int k = 0; k < NS; ++k)
+              if ((k & 1) == sub) F2(fp.F2new[qq], k)[i] = f2[k];
         }
         const double dtq = fc->dtq[qq] * fp.dt;
 #pragma unroll
@@ -1236,10 +1260,12 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
         double rho, u[3], Y[NS], T, f2[NS];
         errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
         production_pair(rho, T, Y, f2);
+        if (valid)
 #pragma unroll
-        for (int k = 0; k < NS; ++k)
-          if ((k & 1) == sub) F2(fp.F2new[nq], k)[i] = f2[k];
+          for (int k = 0; k < NS; ++k)
+            if ((k & 1) == sub) F2(fp.F2new[nq], k)[i] = f2[k];
       }
+      if (!valid) continue;
       if (errs) atomicOr(err, errs);
 #pragma unroll
       for (int q = 0; q < NU; ++q)
@@ -1251,13 +1277,14 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
 // k_mr_src and k_mr_pair in one kernel for four coarse nodes and four fine
 // sub-steps above nine species: the increments of eq. (mrupdate) are formed in
 // registers with k_mr_src's arithmetic and consumed by k_mr_pair's sub-steps,
-// so they never reach HBM.  The lanes of a pair (32 apart in a wave) split the
-// species: lane sub owns the species k with k mod 2 = sub, their 4 increments
-// and partial densities; both lanes run the five non-species components
-// through the sub-steps (their increments need only f1).  Before every
-// temperature solve the pair exchanges its species densities through the
-// cell's LDS column, so both lanes solve with every density and the same
-// operations as k_mr_pair: the results equal the two-kernel form bit for bit.
+// so they never reach HBM.  The lanes of a pair split the species: lane sub
+// owns the species k with k mod 2 = sub, their 4 increments and partial
+// densities; both lanes run the five non-species components through the
+// sub-steps (their increments need only f1).  Before every temperature solve
+// the pair exchanges its species densities through the cell's LDS column, so
+// both lanes solve with every density and the same operations as k_mr_pair:
+// the results equal the two-kernel form bit for bit.  Launched with 256
+// threads whatever the tile.
 template <int NS>
 __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restrict__ boxes,
                                                           const Item *__restrict__ items, int nitems,
@@ -1268,32 +1295,21 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
   constexpr int NK = (NS + 1) / 2;   // species per lane (the even lane one more for odd NS)
   __shared__ double col[3 * A];
   __shared__ double tab[64];
-  __shared__ int rsp[NSDC_NRMAX][4];
-  __shared__ double rco[NSDC_NRMAX][4];
-  const int nr = m->nr;
   for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = m->e2tab[j];
-  for (int j = threadIdx.x; j < nr; j += blockDim.x) {
-    rsp[j][0] = m->rs[j][0] * CS;
-    rsp[j][1] = m->rs[j][1] * CS;
-    rsp[j][2] = m->ps[j][0] * CS;
-    rsp[j][3] = m->ps[j][1] * CS;
-    rco[j][0] = m->lnA[j];
-    rco[j][1] = m->beta[j];
-    rco[j][2] = m->EaR[j];
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, slot = (threadIdx.x >> 6) * 32 + (lane & 31), sub = lane >> 5;
-  double *sh = col + slot;
+  const PairLane pl;
+  const int sub = pl.sub;
+  double *sh = col + pl.slot;
   // as in k_mr_pair
   auto production_pair = [&](double rho, double T, const double *Y, double *wdot) {
-    pair_rates<NS, CS>(m, rho, T, Y, sh, sub, rsp, rco, tab, nr);
+    pair_rates<NS, CS>(m, rho, T, Y, sh, sub, tab);
     // this lane's species only
 #pragma unroll
     for (int n = 0; n < NK; ++n) {
       const int k = 2 * n + sub;
-      if (k < NS) wdot[n] = sh[2 * A + k * CS] * m->W[k];
+      if (k < NS) wdot[n] = (sh[A + k * CS] + sh[2 * A + k * CS]) * m->W[k];
     }
   };
+  const int tcells = ts.tx * ts.ty * ts.tz;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item w = items[it];
     const BoxDev b = boxes[w.box];
@@ -1305,12 +1321,9 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
     auto F2 = [&](int sl, int k) { return fp.F2base + (sl * fp.f2slot + o2 + k * nI); };
     const int n1 = fc->n1, nf = fc->nfine;
     const double dt = fp.dt;
-    for (int h = 0; h < 2; ++h) {
-      const int cell = h * (int)(blockDim.x >> 1) + slot;
-      const int x = w.x0 + cell % ts.tx, y = w.y0 + (cell / ts.tx) % ts.ty, z = w.z0 + cell / (ts.tx * ts.ty);
-      if (cell >= ts.tx * ts.ty * ts.tz || x >= b.nx || y >= b.ny || z >= b.nz) continue;
-      const unsigned s = ((unsigned)(z + NSDC_NG) * b.sy + (y + NSDC_NG)) * b.sx + (x + NSDC_NG);
-      const unsigned i = ((unsigned)z * b.ny + y) * b.nx + x;
+    for (int h = 0; h < tcells; h += CS) {
+      unsigned s, i;
+      const bool valid = pair_cell(w, b, ts, h, pl.slot, s, i);
       // increments of component q for the NQ sub-steps, k_mr_src's arithmetic
       auto increments = [&](int q, double *inc) {
         asm volatile("" ::: "memory");
@@ -1388,15 +1401,15 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
       // both lanes' species densities through the cell's column, then the
       // temperature solve of sub-step r as cell_state does it
       auto state = [&](int r, double &rho, double *Y, double &T, double T0) {
-        wave_sync();   // the previous readers of the column are done
+        __syncthreads();   // the previous readers of the columns are done
 #pragma unroll
         for (int n = 0; n < NK; ++n)
-          if (2 * n + sub < NS) sh[2 * A + (2 * n + sub) * CS] = Uk[n];
-        wave_sync();
+          if (2 * n + sub < NS) sh[(2 * n + sub) * CS] = Uk[n];
+        __syncthreads();
         rho = rho_r[r];
         const double ir = 1.0 / rho;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) Y[k] = sh[2 * A + k * CS] * ir;
+        for (int k = 0; k < NS; ++k) Y[k] = sh[k * CS] * ir;
         int e = rho > 0.0 ? 0 : NSDC_ERR_RHO;
         e |= temperature<NS>(m, Y, e_r[r], T, T0);
         return e;
@@ -1414,9 +1427,10 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
           errs |= state(qq, rho, Y, T, Tprev);
           Tprev = T;
           production_pair(rho, T, Y, f2);
+          if (valid)
 #pragma unroll
-          for (int n = 0; n < NK; ++n)
-            if (2 * n + sub < NS) F2(fp.F2new[qq], 2 * n + sub)[i] = f2[n];
+            for (int n = 0; n < NK; ++n)
+              if (2 * n + sub < NS) F2(fp.F2new[qq], 2 * n + sub)[i] = f2[n];
         }
         const double dtq = fc->dtq[qq] * dt;
 #pragma unroll
@@ -1427,10 +1441,12 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
         double rho, Y[NS], T, f2[NK];
         errs |= state(NQ, rho, Y, T, Tprev);
         production_pair(rho, T, Y, f2);
+        if (valid)
 #pragma unroll
-        for (int n = 0; n < NK; ++n)
-          if (2 * n + sub < NS) F2(fp.F2new[NQ], 2 * n + sub)[i] = f2[n];
+          for (int n = 0; n < NK; ++n)
+            if (2 * n + sub < NS) F2(fp.F2new[NQ], 2 * n + sub)[i] = f2[n];
       }
+      if (!valid) continue;
       if (errs) atomicOr(err, errs);
 #pragma unroll
       for (int q = 0; q < 5; ++q)
@@ -2148,8 +2164,8 @@ struct Launch {
     if constexpr (NS > 9) {
       if (fp.nq == 4 && fp.n1 == 4 && c.fused_fine) {
         prof_begin(c.prof, K_MR_FINE, c.stream);
-        hipLaunchKernelGGL(k_mr_pair_fused<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin,
-                           Uout, fc, fp, c.mech, c.err);
+        hipLaunchKernelGGL(k_mr_pair_fused<NS>, grid, dim3(256), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI,
+                           Uin, Uout, fc, fp, c.mech, c.err);
         prof_end(c.prof, K_MR_FINE, c.stream);
         return;
       }
@@ -2163,10 +2179,8 @@ struct Launch {
                          aslot);
     prof_end(c.prof, K_MR_SRC, c.stream);
     prof_begin(c.prof, K_MR_FINE, c.stream);
-    // (interior tiles are whole waves, at most 256 threads, as k_mr_pair needs:
-    // sdc_set_tiles and the tile choices of the library keep them so)
     if constexpr (NS > 9)
-      hipLaunchKernelGGL(k_mr_pair<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
+      hipLaunchKernelGGL(k_mr_pair<NS>, grid, dim3(256), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
                          fp, A, aslot, c.mech, c.err);
     else
       hipLaunchKernelGGL(k_mr_step<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,

@@ -18,6 +18,12 @@
 #define NSDC_MAXNODES 40
 #define NSDC_MAXFINE 33
 
+namespace nsdc {
+constexpr double RU = 8.31446261815324;               // J / (mol K)
+constexpr double PREF = 101325.0;                     // Pa, the Gibbs energies' reference pressure
+constexpr double LN_RU_PREF = -9.408091968943316;     // ln(RU / PREF)
+}  // namespace nsdc
+
 // device error word bits
 #define NSDC_ERR_NEWTON 1
 #define NSDC_ERR_TRANGE 2
@@ -27,7 +33,7 @@
 // Mechanism tables in device memory.  Thermodynamic polynomials are stored
 // pre-scaled for Horner evaluation of c_p/R, h/(RT) and s/R; reactions as
 // two reactant and two product species indices (ns = no molecule: a dummy
-// species of unit concentration and zero Gibbs energy).
+// species of unit concentration).
 struct DevMech {
   int ns, nr;
   double Tlo, Thi;
@@ -41,6 +47,10 @@ struct DevMech {
   // g/(RT) = h/(RT) - s/R = gc0 - a1 ln T + T (gc1 + T (gc2 + T (gc3 + T gc4))) + a6 / T
   double gc[NSDC_NSMAX][5];   // a1 - a7, -a2/2, -a3/6, -a4/12, -a5/20
   double lnA[NSDC_NRMAX], beta[NSDC_NRMAX], EaR[NSDC_NRMAX];
+  // ln k_f - G_r0 - G_r1 (G = g/RT, the dummy slot's G = -ln(R T / p_ref))
+  // as one function of T: xc0 + xc1 ln T + xc2 / T + T (xc3 + T (xc4 + T
+  // (xc5 + T xc6))); xc7 pads the row to 64 bytes
+  double xc[NSDC_NRMAX][8];
   int rs[NSDC_NRMAX][2], ps[NSDC_NRMAX][2];
   int dnu[NSDC_NRMAX];
   double M[8][8];             // narrow-stencil matrix, [m+3][n+3]

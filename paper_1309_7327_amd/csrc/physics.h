@@ -9,10 +9,6 @@
 
 namespace nsdc {
 
-constexpr double RU = 8.31446261815324;
-constexpr double PREF = 101325.0;
-constexpr double LN_RU_PREF = -9.408091968943316;  // ln(RU / PREF)
-
 // e^x for the reaction rates: x = k ln2/64 + r with k = rint(64 x / ln 2) and
 // |r| <= ln2/128 (Cody-Waite reduction with a two-part ln2/64 whose leading
 // part has 37 significant bits, so k times it is exact for |k| < 2^16), e^r
@@ -118,34 +114,36 @@ __device__ int temperature(const DevMech *__restrict__ m, const double *Y, doubl
 // Every reaction has two reactant and two product slots; an absent molecule
 // points at slot NS, a dummy species.  The rate of progress is formed with
 // one exponential per reaction: with G_k = g_k/RT, b_k = c_k exp(G_k) and the
-// dummy slot's G = -ln(R T / p_ref), c = 1 (so that sum nu = the number of
-// absent reactant molecules minus absent product molecules is carried by
-// the slots),
+// dummy slot's G = -ln(R T / p_ref), c = 1 (so that sum nu, the absent
+// reactant molecules minus the absent product molecules, is carried by the
+// slots),
 //   q = k_f c_r0 c_r1 - k_r c_p0 c_p1 = exp(ln k_f - G_r0 - G_r1) (b_r0 b_r1 - b_p0 b_p1),
-// which costs NS + 1 exponentials per cell for the b_k instead of one more
-// per reaction.  The loop body has no branches.
+// and the exponent is one polynomial in T per reaction (DevMech::xc, the
+// reactants' NASA coefficients folded in).  Per cell that costs NS + 1
+// exponentials for the b_k instead of one more per reaction.
+__device__ __forceinline__ double rate_exponent(const DevMech *__restrict__ m, int j, double T, double invT,
+                                                double lnT) {
+  const double *x = m->xc[j];
+  return fma(x[2], invT, fma(x[1], lnT, fma(T, x[3] + T * (x[4] + T * (x[5] + T * x[6])), x[0])));
+}
 template <int NS>
 __device__ void production(const DevMech *__restrict__ m, double rho, double T, const double *Y,
                            double *wdot) {
-  double b[NS + 1], g[NS + 1], w[NS + 1];
+  double b[NS + 1], w[NS + 1];
   const double lnT = log(T), invT = 1.0 / T;
   const double lnRTp = lnT + LN_RU_PREF;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    g[k] = g_RT(m, k, T, invT, lnT);
-    b[k] = rho * Y[k] * m->invW[k] * exp(g[k]);
+    b[k] = rho * Y[k] * m->invW[k] * exp(g_RT(m, k, T, invT, lnT));
     w[k] = 0.0;
   }
-  g[NS] = -lnRTp;
   b[NS] = exp(-lnRTp);
   w[NS] = 0.0;
   const int nr = m->nr;
 #pragma unroll 2
   for (int j = 0; j < nr; ++j) {
     const int r0 = m->rs[j][0], r1 = m->rs[j][1], p0 = m->ps[j][0], p1 = m->ps[j][1];
-    const double lnkf = m->lnA[j] + m->beta[j] * lnT - m->EaR[j] * invT;
-    const double kf = exp(lnkf - (g[r0] + g[r1]));
-    const double q = kf * (b[r0] * b[r1] - b[p0] * b[p1]);
+    const double q = exp(rate_exponent(m, j, T, invT, lnT)) * (b[r0] * b[r1] - b[p0] * b[p1]);
     w[r0] -= q;
     w[r1] -= q;
     w[p0] += q;
@@ -155,13 +153,14 @@ __device__ void production(const DevMech *__restrict__ m, double rho, double T, 
   for (int k = 0; k < NS; ++k) wdot[k] = w[k] * m->W[k];
 }
 
-// The same source with the per-cell arrays b, g and w in this thread's LDS
+// The same source with the per-cell arrays b, G and w in this thread's LDS
 // column: entry k of array a at sh[(a (NS+1) + k) 256] (consecutive threads
 // own consecutive doubles).  A species index then costs one address add
-// shared by the three arrays, instead of indexed register moves.  The
-// exponentials use exp_tab with the workgroup's copy of the 2^(j/64) table
-// (64 doubles after the three arrays); every other operation and its order
-// is the same as in production().
+// shared by the three arrays, instead of indexed register moves.  Here the
+// exponent is ln k_f - G_r0 - G_r1 from the cell's G_k (two LDS reads instead
+// of production()'s seven-coefficient polynomial per reaction: the faster
+// form with a lane per cell).  The exponentials use exp_tab with the
+// workgroup's copy of the 2^(j/64) table (64 doubles after the three arrays).
 template <int NS, int LIMIT = 65536>
 constexpr bool chem_in_lds() {
   return (3 * (NS + 1) * 256 + 64) * sizeof(double) <= LIMIT;
