@@ -162,7 +162,7 @@ int rhs_eval(sdc_context *ctx, const box_desc *box, double *U, double *dUdt, uns
  * other device or pinned allocation (the context's creation set up the
  * array's address and a pinned staging buffer for the work list, which the
  * call copies to the device on `stream`).
- * Limit: the box's scratch (work list, (8 + 3 ns + 9) doubles per ghosted
+ * Limit: the box's scratch (work list, (18 + 3 ns) doubles per ghosted
  * cell) must fit NSDC_STATIC_SCRATCH_BYTES, e.g. a 48^3 box with 9 species
  * or a 32^3 box with 21; larger boxes return SDC_EINVAL (use rhs_eval).
  * Every call on one GPU shares that GPU's array and it keeps the last call's

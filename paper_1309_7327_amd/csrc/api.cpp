@@ -610,7 +610,7 @@ struct WsLayout {
 
 WsLayout ws_layout(const Plan *p, int ns, const sdc_scheme *s) {
   WsLayout w{};
-  const int nU = 5 + ns, nP = 9 + 3 * ns;
+  const int nU = 5 + ns, nP = prim_fields(ns);
   const int M1 = s->n_coarse - 1;
   if (s->n_fine != 0 && s->mode == 2) {
     // mode 2: F1 = chemistry at the coarse nodes (ns per cell), F2 =
@@ -1311,7 +1311,7 @@ int rhs_eval(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsig
   rc = get_plan(c, 1, box, nullptr, &pl);
   if (rc) return rc;
   const int ns = c->ops->ns;
-  const size_t need = ((size_t)pl->totS * (9 + 3 * ns + 9) + 64) * sizeof(double);
+  const size_t need = ((size_t)pl->totS * (prim_fields(ns) + 9) + 64) * sizeof(double);
   if (need > c->scratch_bytes) {
     HIPCHECK(c, hipStreamSynchronize((hipStream_t)stream));
     if (c->scratch) (void)hipFree(c->scratch);
@@ -1321,7 +1321,7 @@ int rhs_eval(sdc_context *c, const box_desc *box, double *U, double *dUdt, unsig
     c->scratch_bytes = need;
   }
   double *P = c->scratch;
-  double *G = P + ((((size_t)pl->totS * (9 + 3 * ns)) + 31) & ~size_t(31));
+  double *G = P + ((((size_t)pl->totS * prim_fields(ns)) + 31) & ~size_t(31));
   const Range range("rhs_eval");
   const LaunchCtx l = make_lc(c, pl, (hipStream_t)stream);
   eval_rhs_g(c->ops, l, FRef{U, nullptr}, P, G, FRef{dUdt, nullptr}, parts);
@@ -1352,7 +1352,7 @@ int rhs_eval_static(sdc_context *c, const box_desc *box, double *U, double *dUdt
   auto up256 = [](size_t n) { return (n + 255) & ~size_t(255); };
   const size_t off_items = up256(sizeof(BoxDev));
   const size_t off_P = up256(off_items + sizeof(Item) * items.size());
-  const size_t off_G = up256(off_P + sizeof(double) * (size_t)p.totS * (9 + 3 * ns));
+  const size_t off_G = up256(off_P + sizeof(double) * (size_t)p.totS * prim_fields(ns));
   const size_t need = off_G + sizeof(double) * ((size_t)p.totS * 9 + 64);
   if (need > NSDC_STATIC_SCRATCH_BYTES)
     return fail(c, SDC_EINVAL, "box needs " + std::to_string(need) + " bytes of static scratch, more than its " +
@@ -1704,7 +1704,7 @@ struct VjpLayout {
 };
 VjpLayout vjp_layout(const Plan *p, int ns, int nr, int cap) {
   VjpLayout w{};
-  const int nU = 5 + ns, nP = 9 + 3 * ns;
+  const int nU = 5 + ns, nP = prim_fields(ns);
   size_t off = 0;
   auto take = [&](size_t n) {
     size_t o = off;

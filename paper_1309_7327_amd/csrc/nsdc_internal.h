@@ -19,6 +19,8 @@
 #define NSDC_MAXFINE 33
 
 namespace nsdc {
+// primitive fields stored per ghosted cell (their order: Layout, physics.h)
+__host__ __device__ constexpr int prim_fields(int ns) { return 9 + 3 * ns; }
 constexpr double RU = 8.31446261815324;               // J / (mol K)
 constexpr double PREF = 101325.0;                     // Pa, the Gibbs energies' reference pressure
 constexpr double LN_RU_PREF = -9.408091968943316;     // ln(RU / PREF)

@@ -42,7 +42,8 @@ struct Layout {
   // primitive fields stored per cell
   static constexpr int PU = 0, PV = 1, PW = 2, PT = 3, PP = 4, PMU = 5, PLAM = 6, PRD = 7;
   static constexpr int PY = 8, PX = 8 + NS, PH = 8 + 2 * NS, PWB = 8 + 3 * NS;
-  static constexpr int NP = 9 + 3 * NS;
+  static constexpr int NP = prim_fields(NS);
+  static_assert(NP == PWB + 1, "the primitive field count follows the layout");
 };
 
 __device__ __forceinline__ double d1(const double *f, double idx) {
