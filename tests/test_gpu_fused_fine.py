@@ -121,8 +121,11 @@ def test_two_lanes_per_cell_with_an_odd_reaction_count():
 
 def test_two_lanes_per_cell_is_deterministic():
     """The paired-lane sub-step kernel sums a cell's production from its two
-    lanes through LDS atomics: repeated 21-species multirate steps (several
-    workgroups, ragged tail) and another tile shape give the same bits."""
+    lanes (in two waves, each lane into its own array, the two added in a
+    fixed order): repeated 21-species multirate steps (several workgroups,
+    ragged tail) and other tile shapes give the same bits, among them tiles of
+    64 and 192 cells, whose passes of 128 cell slots leave slots without a
+    cell (they compute on the tile's first cell and store nothing)."""
     m = mechanism.load("mech21")
     shape = (20, 18, 40)
     prim = fields.sines(shape, 1e-4, m["ns"], 37)
@@ -131,7 +134,7 @@ def test_two_lanes_per_cell_is_deterministic():
     ctx = N.Context(0)
     ctx.set_mechanism(m)
     outs = []
-    for tiles in [None, None, ((16, 4, 4), (16, 4, 4))]:
+    for tiles in [None, None, ((16, 4, 4), (16, 4, 4)), ((8, 8, 1), (16, 4, 4)), ((16, 4, 3), (16, 4, 4))]:
         if tiles is not None:
             ctx.set_tiles(*tiles, grid_cap=37)
         bx, U = G.device_state(ctx, prim, 1e-4)
