@@ -133,12 +133,13 @@ __global__ __launch_bounds__(256) void k_ghost(const BoxDev *__restrict__ boxes,
 
 // out_mode: 0 leave the right-hand side alone, 1 zero it, 2 chemistry source
 // (only the CHEM instance takes mode 2: without the chemistry the kernel
-// needs fewer registers: 164 instead of 218 at 9 species, three waves per
-// SIMD instead of two).
+// needs fewer registers, and it is held to three waves per SIMD, 168
+// registers: at 21 species the compiler's 183 registers allowed two waves
+// and the kernel took 12% longer).
 // warm != 0: start the Newton solve from the temperature the previous
 // evaluation left in P (when it lies in the fit range), else from 1000 K.
 template <int NS, bool CHEM>
-__global__ __launch_bounds__(256) void k_prims(const BoxDev *__restrict__ boxes,
+__global__ __launch_bounds__(256, CHEM ? 2 : 3) void k_prims(const BoxDev *__restrict__ boxes,
                                                const Item *__restrict__ items, int nitems,
                                                TileShape ts, FRef Uref, double *__restrict__ Pbase,
                                                FRef Fout, int out_mode, int warm, int store_x,
