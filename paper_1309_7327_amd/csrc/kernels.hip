@@ -1094,8 +1094,9 @@ __global__ __launch_bounds__(256) void k_mr_step(const BoxDev *__restrict__ boxe
 }
 
 // Orders the LDS accesses of the lanes of one wave (the two lanes that share
-// a cell in k_mr_pair are in one wave; a wave executes its LDS
-// instructions in issue order, so only the compiler must not move them).
+// a cell's slot in the two-lane implicit chemistry kernel are in one wave; a
+// wave executes its LDS instructions in issue order, so only the compiler
+// must not move them).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
