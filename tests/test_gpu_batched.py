@@ -176,3 +176,36 @@ def test_batched_variants_equal_per_box_loop(variant):
     for a, b in zip(Ub, Ul):
         assert torch.equal(G.interior(a), G.interior(b))
     ctx.close()
+
+
+def test_batched_21_species_multirate_equals_per_box_loop():
+    """Above nine species the fine sweep runs on lane pairs in two waves,
+    launched with 256 threads whatever the tile: a batch of ragged boxes (one
+    tile shape for all, so tiles cross the boxes' edges) gives the bits of the
+    per-box loop (each box with its own default tile)."""
+    m = mechanism.load("mech21")
+    ctx = N.Context(0)
+    ctx.set_mechanism(m)
+    shapes = [(13, 9, 7), (24, 16, 16), (40, 11, 6)]
+    dt = time_step("box16_sdc")
+    sch = N.scheme(4, 2, 5, 1)
+
+    def states():
+        boxes, Us = [], []
+        for j, sh in enumerate(shapes):
+            bx, U = G.device_state(ctx, fields.sines(sh, 1e-4, m["ns"], 50 + j), 1e-4)
+            boxes.append(bx)
+            Us.append(U)
+        return boxes, Us
+
+    boxes, Ub = states()
+    _, Ul = states()
+    ctx.profile(True)
+    _run_batched(ctx, boxes, Ub, sch, 1, dt)
+    prof = ctx.profile_read()
+    assert "mr_fine" in prof and "mr_src" not in prof
+    ctx.profile(False)
+    _run_loop(ctx, boxes, Ul, sch, 1, dt)
+    for a, b in zip(Ub, Ul):
+        assert torch.equal(G.interior(a), G.interior(b)), float((G.interior(a) - G.interior(b)).abs().max())
+    ctx.close()
