@@ -1293,7 +1293,7 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
                                                           TileShape ts, FRef Uin, FRef Uout,
                                                           const FineCoef *__restrict__ fc, FinePtrs fp,
                                                           const DevMech *__restrict__ m, int *err) {
-  constexpr int NU = 5 + NS, CS = 128, A = (NS + 1) * CS, NQ = 4;
+  constexpr int NU = 5 + NS, CS = 128, A = (NS + 1) * CS, NQ = 4, N1 = 4;
   constexpr int NK = (NS + 1) / 2;   // species per lane (the even lane one more for odd NS)
   __shared__ double col[3 * A];
   __shared__ double tab[64];
@@ -1321,17 +1321,19 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
     double *Uo = Uout.get(w.box, b.offS * NU);
     auto F1 = [&](int sl, int q) { return fp.F1base + (sl * fp.f1slot + o1 + q * nI); };
     auto F2 = [&](int sl, int k) { return fp.F2base + (sl * fp.f2slot + o2 + k * nI); };
-    const int n1 = fc->n1, nf = fc->nfine;
     const double dt = fp.dt;
     for (int h = 0; h < tcells; h += CS) {
       unsigned s, i;
       const bool valid = pair_cell(w, b, ts, h, pl.slot, s, i);
       // increments of component q for the NQ sub-steps, k_mr_src's arithmetic
+      // (four coarse nodes: k_mr_src's sums without its zero terms; the S22
+      // rows padded with zeros to the interval's five fine nodes add exact
+      // zeros)
       auto increments = [&](int q, double *inc) {
         asm volatile("" ::: "memory");
-        double f1[8];
+        double f1[N1];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) f1[j] = j < n1 ? F1(fp.F1old[j], q)[i] : 0.0;
+        for (int j = 0; j < N1; ++j) f1[j] = F1(fp.F1old[j], q)[i];
         const double dF1 = F1(fp.F1new_p, q)[i] - F1(fp.F1old_p, q)[i];
         double g[NQ + 1];
         if (q >= 5) {
@@ -1343,16 +1345,12 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restri
           const double dtq = fc->dtq[r] * dt;
           double acc = 0.0;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) acc += fc->S21[r][j] * f1[j];
+          for (int j = 0; j < N1; ++j) acc += fc->S21[r][j] * f1[j];
           double v = dtq * dF1 + dt * acc;
           if (q >= 5) {
-            const int jlo = fc->jlo[r];
             double s22 = 0.0;
 #pragma unroll
-            for (int j = 0; j <= NQ; ++j) {
-              const int jj = j - jlo;
-              if (jj >= 0 && jj < nf) s22 += fc->S22[r][jj] * g[j];
-            }
+            for (int j = 0; j <= NQ; ++j) s22 += fc->S22n[r][j] * g[j];
             v += dt * s22 - dtq * g[r];
           }
           inc[r] = v;
