@@ -126,3 +126,45 @@ def test_residual_exit_steps_replay_from_graphs():
     finally:
         ctx.set_graph(False)
         ctx.close()
+
+
+def test_batched_residual_exit_steps_replay_from_graphs():
+    """The same for a batch of boxes sharing the exit decision: replays of a
+    two-step sdc_step_batched call give the eager call's states, residuals
+    and sweep count bit for bit."""
+    mech = mechanism.load("mech9")
+    ctx = N.Context(0)
+    ctx.set_mechanism(mech)
+    ctx.set_residual_exit(30.0)
+    boxes, init = [], []
+    for shape, seed in (((8, 8, 8), 13), ((6, 5, 7), 21)):
+        bx, U = G.device_state(ctx, fields.sines(shape, DX, 9, seed), DX)
+        boxes.append(bx)
+        init.append(U)
+    dt = time_step("box16_sdc")
+    stream = torch.cuda.Stream()
+    sch = N.scheme(4, 14, 0, 1)
+    ws, nb = N.workspace(ctx, boxes, sch)
+    work = [u.clone() for u in init]
+    ctx.sdc_step_batched(boxes, work, dt, 2, sch, ws, nb, stream=stream.cuda_stream)
+    ctx.check_status(stream.cuda_stream)
+    ref = [G.host(G.interior(u)) for u in work]
+    ref_norms, ref_sweeps = ctx.residual_history()
+    assert 0 < ref_sweeps < 2 * 14 and len(ref_norms) > 0
+    ctx.set_graph(True)
+    try:
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                for w, u in zip(work, init):
+                    w.copy_(u)
+            stream.synchronize()
+            ctx.sdc_step_batched(boxes, work, dt, 2, sch, ws, nb, stream=stream.cuda_stream)
+            ctx.check_status(stream.cuda_stream)
+            for w, r in zip(work, ref):
+                assert np.array_equal(G.host(G.interior(w)), r), rep
+            norms, sweeps = ctx.residual_history()
+            assert sweeps == ref_sweeps and np.array_equal(norms, ref_norms), rep
+            torch.cuda.synchronize()
+    finally:
+        ctx.set_graph(False)
+        ctx.close()
