@@ -1107,9 +1107,10 @@ __device__ __forceinline__ void wave_sync() {
 // (b_k and two production arrays: 3 (Ns+1) doubles, 528 bytes at 21 species)
 // would allow one wave per SIMD with a lane per cell; two lanes sharing a
 // cell's column halve the LDS per lane, so two waves per SIMD fit.  The two
-// lanes of a cell are lane l of waves 2v and 2v + 1 of a 256-thread
-// workgroup (cell slot 64 v + l): the lane's half, sub = the wave's parity, is
-// uniform over a wave, so the species and reactions a lane takes are the
+// lanes of a cell are lane l of the two waves of a 128-thread workgroup
+// (cell slot l; a workgroup per pair of waves, so that the pair's barriers
+// hold no other waves): the lane's half, sub = its wave, is uniform over a
+// wave, so the species and reactions a lane takes are the
 // same for its whole wave and their coefficients come from scalar loads of
 // the mechanism.  Each lane sums its reactions' contributions into its own
 // production array, in reaction order, and the two arrays are added in a
@@ -1178,7 +1179,7 @@ __device__ __forceinline__ void pair_rates(const DevMech *__restrict__ m, double
   __syncthreads();
 }
 
-// The cell of pass h (a multiple of 128) of a work item for pair slot `slot`:
+// The cell of pass h (a multiple of 64) of a work item for pair slot `slot`:
 // false (and the tile's first cell, which every work item has) when the slot
 // has no cell in this pass.
 __device__ __forceinline__ bool pair_cell(const Item &w, const BoxDev &b, const TileShape &ts, int h, int slot,
@@ -1199,15 +1200,15 @@ __device__ __forceinline__ bool pair_cell(const Item &w, const BoxDev &b, const 
 // k_mr_step on lane pairs (above): both lanes of a pair run the cell's state
 // update and Newton solve (redundantly, same values) and split the species
 // setup and the reactions (pair_rates); each lane writes half of the outputs.
-// Launched with 256 threads whatever the tile: 128 cells per pass.
+// Launched with 128 threads whatever the tile: 64 cells per pass.
 template <int NS>
-__global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ boxes,
+__global__ __launch_bounds__(128, 2) void k_mr_pair(const BoxDev *__restrict__ boxes,
                                                     const Item *__restrict__ items, int nitems,
                                                     TileShape ts, FRef Uin, FRef Uout,
                                                     const FineCoef *__restrict__ fc, FinePtrs fp,
                                                     const double *__restrict__ Abase, long long aslot,
                                                     const DevMech *__restrict__ m, int *err) {
-  constexpr int NU = 5 + NS, CS = 128, A = (NS + 1) * CS;
+  constexpr int NU = 5 + NS, CS = 64, A = (NS + 1) * CS;
   __shared__ double col[3 * A];
   __shared__ double tab[64];
   for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = m->e2tab[j];
@@ -1285,15 +1286,15 @@ __global__ __launch_bounds__(256, 2) void k_mr_pair(const BoxDev *__restrict__ b
 // sub-steps (their increments need only f1).  Before every temperature solve
 // the pair exchanges its species densities through the cell's LDS column, so
 // both lanes solve with every density and the same operations as k_mr_pair:
-// the results equal the two-kernel form bit for bit.  Launched with 256
+// the results equal the two-kernel form bit for bit.  Launched with 128
 // threads whatever the tile.
 template <int NS>
-__global__ __launch_bounds__(256, 2) void k_mr_pair_fused(const BoxDev *__restrict__ boxes,
+__global__ __launch_bounds__(128, 2) void k_mr_pair_fused(const BoxDev *__restrict__ boxes,
                                                           const Item *__restrict__ items, int nitems,
                                                           TileShape ts, FRef Uin, FRef Uout,
                                                           const FineCoef *__restrict__ fc, FinePtrs fp,
                                                           const DevMech *__restrict__ m, int *err) {
-  constexpr int NU = 5 + NS, CS = 128, A = (NS + 1) * CS, NQ = 4, N1 = 4;
+  constexpr int NU = 5 + NS, CS = 64, A = (NS + 1) * CS, NQ = 4, N1 = 4;
   constexpr int NK = (NS + 1) / 2;   // species per lane (the even lane one more for odd NS)
   __shared__ double col[3 * A];
   __shared__ double tab[64];
@@ -2164,7 +2165,7 @@ struct Launch {
     if constexpr (NS > 9) {
       if (fp.nq == 4 && fp.n1 == 4 && c.fused_fine) {
         prof_begin(c.prof, K_MR_FINE, c.stream);
-        hipLaunchKernelGGL(k_mr_pair_fused<NS>, grid, dim3(256), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI,
+        hipLaunchKernelGGL(k_mr_pair_fused<NS>, grid, dim3(128), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI,
                            Uin, Uout, fc, fp, c.mech, c.err);
         prof_end(c.prof, K_MR_FINE, c.stream);
         return;
@@ -2180,7 +2181,7 @@ struct Launch {
     prof_end(c.prof, K_MR_SRC, c.stream);
     prof_begin(c.prof, K_MR_FINE, c.stream);
     if constexpr (NS > 9)
-      hipLaunchKernelGGL(k_mr_pair<NS>, grid, dim3(256), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
+      hipLaunchKernelGGL(k_mr_pair<NS>, grid, dim3(128), 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,
                          fp, A, aslot, c.mech, c.err);
     else
       hipLaunchKernelGGL(k_mr_step<NS>, grid, block, 0, c.stream, c.boxes, c.itemsI, c.nI, c.tsI, Uin, Uout, fc,

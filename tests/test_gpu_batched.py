@@ -180,7 +180,7 @@ def test_batched_variants_equal_per_box_loop(variant):
 
 def test_batched_21_species_multirate_equals_per_box_loop():
     """Above nine species the fine sweep runs on lane pairs in two waves,
-    launched with 256 threads whatever the tile: a batch of ragged boxes (one
+    launched with 128 threads whatever the tile: a batch of ragged boxes (one
     tile shape for all, so tiles cross the boxes' edges) gives the bits of the
     per-box loop (each box with its own default tile)."""
     m = mechanism.load("mech21")

@@ -123,9 +123,9 @@ def test_two_lanes_per_cell_is_deterministic():
     """The paired-lane sub-step kernel sums a cell's production from its two
     lanes (in two waves, each lane into its own array, the two added in a
     fixed order): repeated 21-species multirate steps (several workgroups,
-    ragged tail) and other tile shapes give the same bits, among them tiles of
-    64 and 192 cells, whose passes of 128 cell slots leave slots without a
-    cell (they compute on the tile's first cell and store nothing)."""
+    ragged tail, whose cell slots past the box compute on the tile's first
+    cell and store nothing) and other tile shapes, among them tiles of 64 and
+    192 cells, give the same bits."""
     m = mechanism.load("mech21")
     shape = (20, 18, 40)
     prim = fields.sines(shape, 1e-4, m["ns"], 37)
