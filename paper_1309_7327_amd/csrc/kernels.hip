@@ -1154,9 +1154,9 @@ __device__ __forceinline__ void pair_loop(const DevMech *__restrict__ m, double 
 // calls it; on return the cell's production of slot k is
 // sh[A + k CS] + sh[2 A + k CS].
 template <int NS, int CS>
-__device__ __forceinline__ void pair_rates(const DevMech *__restrict__ m, double rho, double T, const double *Y,
+__device__ __forceinline__ void pair_rates(const DevMech *__restrict__ m, double rho, double T, const double *Yo,
                                            double *sh, int sub, const double *tab) {
-  constexpr int A = (NS + 1) * CS;
+  constexpr int A = (NS + 1) * CS, NK = (NS + 1) / 2;
   const double lnT = log(T), invT = 1.0 / T, lnRTp = lnT + LN_RU_PREF;
   __syncthreads();   // the previous readers of the columns are done
 #pragma unroll
@@ -1164,7 +1164,7 @@ __device__ __forceinline__ void pair_rates(const DevMech *__restrict__ m, double
     const int k0 = 2 * n, k1 = 2 * n + 1;
     if (k1 <= NS || sub == 0) {
       const int k = k0 + sub;
-      const double y = sub ? Y[k1 < NS ? k1 : NS - 1] : Y[k0 < NS ? k0 : NS - 1];
+      const double y = Yo[n < NK ? n : NK - 1];
       sh[k * CS] = k < NS ? rho * y * m->invW[k] * exp_tab(g_RT(m, k, T, invT, lnT), tab) : exp_tab(-lnRTp, tab);
     }
   }
@@ -1217,7 +1217,10 @@ __global__ __launch_bounds__(128, 2) void k_mr_pair(const BoxDev *__restrict__ b
   double *sh = col + pl.slot;
   // the chemistry source of one cell, rates split between the two lanes
   auto production_pair = [&](double rho, double T, const double *Y, double *wdot) {
-    pair_rates<NS, CS>(m, rho, T, Y, sh, sub, tab);
+    double Yo[(NS + 1) / 2];
+#pragma unroll
+    for (int n = 0; n < (NS + 1) / 2; ++n) Yo[n] = sub ? Y[2 * n + 1 < NS ? 2 * n + 1 : NS - 1] : Y[2 * n];
+    pair_rates<NS, CS>(m, rho, T, Yo, sh, sub, tab);
 #pragma unroll
     for (int k = 0; k < NS; ++k) wdot[k] = (sh[A + k * CS] + sh[2 * A + k * CS]) * m->W[k];
   };
@@ -1247,7 +1250,7 @@ __global__ __launch_bounds__(128, 2) void k_mr_pair(const BoxDev *__restrict__ b
           for (int k = 0; k < NS; ++k) f2[k] = F2(fp.F2old[0], k)[i];
         } else {
           double rho, u[3], Y[NS], T;
-          errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
+          errs |= cell_state_pair<NS>(m, Uc, rho, u, Y, T, Tprev);
           Tprev = T;
           production_pair(rho, T, Y, f2);
           if (valid)
@@ -1261,7 +1264,7 @@ __global__ __launch_bounds__(128, 2) void k_mr_pair(const BoxDev *__restrict__ b
       }
       if (fp.eval_last) {
         double rho, u[3], Y[NS], T, f2[NS];
-        errs |= cell_state<NS>(m, Uc, rho, u, Y, T, Tprev);
+        errs |= cell_state_pair<NS>(m, Uc, rho, u, Y, T, Tprev);
         production_pair(rho, T, Y, f2);
         if (valid)
 #pragma unroll
@@ -1284,10 +1287,11 @@ __global__ __launch_bounds__(128, 2) void k_mr_pair(const BoxDev *__restrict__ b
 // owns the species k with k mod 2 = sub, their 4 increments and partial
 // densities; both lanes run the five non-species components through the
 // sub-steps (their increments need only f1).  Before every temperature solve
-// the pair exchanges its species densities through the cell's LDS column, so
-// both lanes solve with every density and the same operations as k_mr_pair:
-// the results equal the two-kernel form bit for bit.  Launched with 128
-// threads whatever the tile.
+// each lane sums the mixture's energy coefficients over its own species and
+// the pair exchanges the two partial sums through the cell's LDS column, so
+// both lanes solve with the same coefficients and operations as k_mr_pair
+// (cell_state_pair): the results equal the two-kernel form bit for bit.
+// Launched with 128 threads whatever the tile.
 template <int NS>
 __global__ __launch_bounds__(128, 2) void k_mr_pair_fused(const BoxDev *__restrict__ boxes,
                                                           const Item *__restrict__ items, int nitems,
@@ -1399,20 +1403,43 @@ __global__ __launch_bounds__(128, 2) void k_mr_pair_fused(const BoxDev *__restri
           for (int r = 0; r < NQ; ++r) Ak[r][n] = 0.0;
         }
       }
-      // both lanes' species densities through the cell's column, then the
-      // temperature solve of sub-step r as cell_state does it
-      auto state = [&](int r, double &rho, double *Y, double &T, double T0) {
-        __syncthreads();   // the previous readers of the columns are done
-#pragma unroll
-        for (int n = 0; n < NK; ++n)
-          if (2 * n + sub < NS) sh[(2 * n + sub) * CS] = Uk[n];
-        __syncthreads();
+      // the temperature solve of sub-step r as cell_state_pair does it; Yo[n]
+      // = Y of this lane's species 2 n + sub
+      auto state = [&](int r, double &rho, double *Yo, double &T, double T0) {
         rho = rho_r[r];
         const double ir = 1.0 / rho;
 #pragma unroll
-        for (int k = 0; k < NS; ++k) Y[k] = sh[k * CS] * ir;
+        for (int n = 0; n < NK; ++n) Yo[n] = Uk[n] * ir;
+        // e_coeffs over this lane's species k = 2 n + sub, in increasing k
+        double p[6], c[6];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < 6; ++q) p[q] = 0.0;
+#pragma unroll
+        for (int n = 0; n < NK; ++n) {
+          const int k = 2 * n + sub;
+          if (k < NS) {
+            const double YR = Yo[n] * m->Rk[k];
+            const double *a = m->hc[k];
+            p[0] += YR * (a[0] - 1.0);
+            p[1] += YR * a[1];
+            p[2] += YR * a[2];
+            p[3] += YR * a[3];
+            p[4] += YR * a[4];
+            p[5] += YR * m->h6[k];
+          }
+        }
+        __syncthreads();   // the previous readers of the columns are done
+#pragma unroll
+        for (int q = 0; q < 6; ++q) sh[(6 * sub + q) * CS] = p[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const double o = sh[(6 * (1 - sub) + q) * CS];
+          c[q] = sub == 0 ? p[q] + o : o + p[q];
+        }
         int e = rho > 0.0 ? 0 : NSDC_ERR_RHO;
-        e |= temperature<NS>(m, Y, e_r[r], T, T0);
+        e |= temperature_c(m, c, e_r[r], T, T0);
         return e;
       };
       int errs = 0;
@@ -1424,10 +1451,10 @@ __global__ __launch_bounds__(128, 2) void k_mr_pair_fused(const BoxDev *__restri
           for (int n = 0; n < NK; ++n)
             if (2 * n + sub < NS) f2[n] = F2(fp.F2old[0], 2 * n + sub)[i];
         } else {
-          double rho, Y[NS], T;
-          errs |= state(qq, rho, Y, T, Tprev);
+          double rho, Yo[NK], T;
+          errs |= state(qq, rho, Yo, T, Tprev);
           Tprev = T;
-          production_pair(rho, T, Y, f2);
+          production_pair(rho, T, Yo, f2);
           if (valid)
 #pragma unroll
             for (int n = 0; n < NK; ++n)
@@ -1439,9 +1466,9 @@ __global__ __launch_bounds__(128, 2) void k_mr_pair_fused(const BoxDev *__restri
           if (2 * n + sub < NS) Uk[n] += Ak[qq][n] + dtq * f2[n];
       }
       if (fp.eval_last) {
-        double rho, Y[NS], T, f2[NK];
-        errs |= state(NQ, rho, Y, T, Tprev);
-        production_pair(rho, T, Y, f2);
+        double rho, Yo[NK], T, f2[NK];
+        errs |= state(NQ, rho, Yo, T, Tprev);
+        production_pair(rho, T, Yo, f2);
         if (valid)
 #pragma unroll
           for (int n = 0; n < NK; ++n)

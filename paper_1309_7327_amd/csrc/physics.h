@@ -77,24 +77,34 @@ __device__ __forceinline__ double s_R(const DevMech *__restrict__ m, int k, doub
 // is a quintic in T whose coefficients are the mass-weighted species
 // coefficients, so the mixture is summed once and every iteration evaluates
 // two short polynomials (e and its derivative, which is c_v).
-template <int NS>
-__device__ int temperature(const DevMech *__restrict__ m, const double *Y, double e, double &T,
-                           double T0 = 1000.0) {
+// e(T) = c5 + T (c0 + T (c1 + T (c2 + T (c3 + T c4)))): the mixture's
+// coefficients, sum_k Y_k R_k times the species' (a1 - 1, a2/2, a3/3, a4/4,
+// a5/5, a6), over the species k = K0, K0 + KS, ... in increasing order.
+template <int NS, int K0 = 0, int KS = 1>
+__device__ __forceinline__ void e_coeffs(const DevMech *__restrict__ m, const double *Y, double *c) {
   // keep the coefficient loads here: hoisted into an enclosing loop, the
   // mechanism tables exceed the scalar registers and are spilled
   asm volatile("" ::: "memory");
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0, c5 = 0.0;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
+  for (int i = 0; i < 6; ++i) c[i] = 0.0;
+#pragma unroll
+  for (int k = K0; k < NS; k += KS) {
     const double YR = Y[k] * m->Rk[k];
     const double *a = m->hc[k];
-    c0 += YR * (a[0] - 1.0);
-    c1 += YR * a[1];
-    c2 += YR * a[2];
-    c3 += YR * a[3];
-    c4 += YR * a[4];
-    c5 += YR * m->h6[k];
+    c[0] += YR * (a[0] - 1.0);
+    c[1] += YR * a[1];
+    c[2] += YR * a[2];
+    c[3] += YR * a[3];
+    c[4] += YR * a[4];
+    c[5] += YR * m->h6[k];
   }
+}
+// Newton's method on e(T) = e from the mixture's coefficients c, de/dT = c_v:
+// start at T0, stop one iteration after the first update below 1e-12 T (at
+// most 50).
+__device__ __forceinline__ int temperature_c(const DevMech *__restrict__ m, const double *c, double e, double &T,
+                                             double T0) {
+  const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
   const double d1 = 2.0 * c1, d2 = 3.0 * c2, d3 = 4.0 * c3, d4 = 5.0 * c4;
   T = T0;
   bool conv = false;
@@ -107,6 +117,13 @@ __device__ int temperature(const DevMech *__restrict__ m, const double *Y, doubl
     if (fabs(dT) <= 1e-12 * fabs(T)) conv = true;
   }
   return NSDC_ERR_NEWTON;
+}
+template <int NS>
+__device__ int temperature(const DevMech *__restrict__ m, const double *Y, double e, double &T,
+                           double T0 = 1000.0) {
+  double c[6];
+  e_coeffs<NS>(m, Y, c);
+  return temperature_c(m, c, e, T, T0);
 }
 
 // Chemistry source rho omega_k (mass action, reversible Arrhenius reactions,
@@ -242,6 +259,30 @@ __device__ int cell_state(const DevMech *__restrict__ m, const double *Uc, doubl
   const double e = Uc[4] * ir - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   int err = rho > 0.0 ? 0 : NSDC_ERR_RHO;
   err |= temperature<NS>(m, Y, e, T, T0);
+  return err;
+}
+
+// cell_state with the mixture's energy coefficients summed as the lane pairs
+// of the fine sweep sum them: over the even and the odd species apart, then
+// the two partial sums added.
+template <int NS>
+__device__ int cell_state_pair(const DevMech *__restrict__ m, const double *Uc, double &rho, double *u,
+                               double *Y, double &T, double T0) {
+  rho = Uc[0];
+  const double ir = 1.0 / rho;
+  u[0] = Uc[1] * ir;
+  u[1] = Uc[2] * ir;
+  u[2] = Uc[3] * ir;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Y[k] = Uc[5 + k] * ir;
+  const double e = Uc[4] * ir - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  double c0[6], c1[6], c[6];
+  e_coeffs<NS, 0, 2>(m, Y, c0);
+  e_coeffs<NS, 1, 2>(m, Y, c1);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c[q] = c0[q] + c1[q];
+  int err = rho > 0.0 ? 0 : NSDC_ERR_RHO;
+  err |= temperature_c(m, c, e, T, T0);
   return err;
 }
 
