@@ -11,8 +11,8 @@ A_j (1 +- h w_A,j); h = 1e-6.  The directional derivative is then
 it to O(h^2) (ln(1 + h w) - ln(1 - h w) = 2 h w + O(h^3)).
 
 Criteria:
-  * central differences: |fd - adj| <= 1e-6 |adj| per direction (the
-    survey's relative step and bound: the truncation error is O(h^2) times
+  * central differences: |fd - adj| <= 1e-6 |adj| per direction (at the
+    relative step 1e-6 the truncation error is O(h^2) times
     third derivatives of the rates, ~1e-9 here, and the FP64 rounding of the
     difference quotient is ~1e-16 |f| / h);
   * oracle: |<vbar, J_oracle w> - adj| <= 1e-10 |adj| (dual-number tangent
