@@ -447,7 +447,7 @@ def run_box(args, workload, steps, warmup, with_baseline):
     # the same number of steps with no events attached, three times (their
     # median per step beside the timed region's figure)
     reps = []
-    for _ in range(3):
+    for _ in range(5):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         ctx.sdc_step(bx, U, dt, steps, sch, ws, nb)
