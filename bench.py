@@ -17,7 +17,7 @@ timed region of exactly K steps; the line also carries Mcell
 advection-diffusion and reaction evaluations per second, the roofline of the
 dominant kernel and of the three stencil direction passes together (average
 durations from HIP events recorded on the launch stream around every launch
-of the timed region), the same K steps timed three more times with no
+of the timed region), the same K steps timed five more times with no
 events attached (their per-step median: unprofiled_ms_per_step), and the
 oracle baseline.
 """
