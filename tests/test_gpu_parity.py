@@ -198,3 +198,44 @@ def test_rhs_eval_other_stencil_parameters(params):
     ok, rep = G.compare(G.host(F), fref, floor)
     print(params, G.fmt(rep))
     assert ok, G.fmt(rep)
+
+
+def _temperature_ramp(m, shape, seed):
+    """Quiescent gas at 1 atm whose temperature runs along x over the
+    mechanism's whole fit range (210 to 3400 K), mixtures drawn per cell: the
+    rate exponents (ln k_f minus the reactants' g/RT, and g/RT itself) reach
+    their largest magnitudes at the two ends."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    T = np.broadcast_to(np.linspace(210.0, 3400.0, nx)[None, None, :], shape).copy()
+    Y = rng.dirichlet(np.ones(m["ns"]), size=shape).transpose(3, 0, 1, 2).copy()
+    return dict(p=np.full(shape, 101325.0), T=T, Y=Y, u=np.zeros((3,) + shape))
+
+
+@pytest.mark.parametrize("kind", ["mech9", "mech12", "mech21"])
+def test_chemistry_over_the_temperature_range(kind):
+    """The kernels' one-exponential rate form against the oracle's two
+    exponentials (forward rate, reverse rate from the equilibrium constant)
+    from 210 to 3400 K: the chemistry source alone, and one multirate step
+    whose fine sub-steps run the paired-lane kernel above nine species."""
+    m, om, ctx = mech(kind)
+    shape, dx = (4, 3, 16), 1e-4
+    prim = _temperature_ramp(m, shape, 7)
+    bx, U, Uo = G.oracle_state(om, prim, dx)
+    F = torch.zeros((5 + m["ns"],) + shape, dtype=torch.float64, device="cuda")
+    ctx.rhs_eval(bx, U, F, N.RHS_REACT)
+    ctx.check_status()
+    fref, floor = G.ulp_floor(lambda V: oracle.rhs(om, V, dx, parts=oracle.REACT), Uo)
+    ok, rep = G.compare(G.host(F), fref, floor)
+    print("R ", G.fmt(rep))
+    assert ok, G.fmt(rep)
+    sch = dict(n_coarse=4, sweeps=2, n_fine=5, fine_repeat=1)
+    dt = 1e-10
+    _run_gpu_sdc(ctx, bx, U, dt, sch, 1)
+    Ug = G.interior(G.host(U))
+    ref, fl, dfl = G.ulp_floor_step(lambda V, pt: _sdc_oracle(om, V, dx, dt, sch, 1, pt), Uo)
+    ok, rep = G.compare(Ug, ref, fl)
+    okd, repd = G.compare(Ug - Uo, ref - Uo, dfl, state=ref)
+    print("U ", G.fmt(rep))
+    print("dU", G.fmt(repd))
+    assert ok and okd, G.fmt(repd)
