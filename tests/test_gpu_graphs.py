@@ -168,3 +168,33 @@ def test_batched_residual_exit_steps_replay_from_graphs():
     finally:
         ctx.set_graph(False)
         ctx.close()
+
+
+def test_21_species_multirate_steps_replay_from_graphs():
+    """The 21-species multirate step (its fine sweep on lane pairs that
+    synchronise their workgroup) captured and replayed: every replay gives
+    the eager call's bits."""
+    mech = mechanism.load("mech21")
+    ctx = N.Context(0)
+    ctx.set_mechanism(mech)
+    bx, U0 = G.device_state(ctx, fields.sines((6, 7, 20), DX, mech["ns"], 29), DX)
+    dt = time_step("box16_sdc")
+    stream = torch.cuda.Stream()
+    sch = N.scheme(4, 2, 5, 1)
+    ctx.set_graph(False)
+    ref = _run(ctx, bx, U0, sch, dt, 2, stream)
+    ctx.set_graph(True)
+    try:
+        U = U0.clone()
+        ws, nb = N.workspace(ctx, [bx], sch)
+        for rep in range(3):
+            with torch.cuda.stream(stream):
+                U.copy_(U0)
+            stream.synchronize()
+            ctx.sdc_step(bx, U, dt, 2, sch, ws, nb, stream=stream.cuda_stream)
+            ctx.check_status(stream.cuda_stream)
+            assert np.array_equal(G.host(G.interior(U)), ref), rep
+            torch.cuda.synchronize()
+    finally:
+        ctx.set_graph(False)
+        ctx.close()
